@@ -1,0 +1,225 @@
+"""Throughput benchmark: order-5 DMAS + CF + envelope on an eRTIS-like frame.
+
+Workload (one "step" = one pass of the whole path over one frame): 32
+microphones in a 12 cm sparse planar aperture, 91 x 46 azimuth/elevation
+directions (2 deg steps), 16384 samples at 450 kHz of matched-filtered chirp
+echoes from 20 reflectors (synthetic, seeded). One step is one
+dmas_envelope() call: steering delays, channel staging, signed roots, power
+sums, Newton-Girard, coherence factor, envelope FIR and store, all in one
+kernel. Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: throughput in direction*samples/s, the dominant kernel's
+roofline position (VALU issue bound), and the FP64 CPU oracle timed on a
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 VALU lane-instruction
+# issue slots per second (the FP32 vector peak of 157.3 TFLOP/s counts an FMA
+# as 2 flops and packed dual-FP32 as 2 lanes; packed FP32 is not used here).
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# Issue cost of the gfx950 transcendentals (v_exp_f32 / v_log_f32 / v_sqrt_f32)
+# in full-rate slots, measured (half rate).
+TRANS_SLOTS = 2
+
+
+def mic_slots(n: int, cf: bool) -> int:
+    """VALU issue slots per microphone per output sample for order n (the method's minimum).
+
+    Root: none (n = 1), sqrt (n = 2), or log2 + scale + exp2 (n >= 3); sign
+    transfer; the intermediate powers that cannot be fused into an FMA
+    accumulation; n power-sum accumulations (P_n is sum x or sum |x|); CF adds
+    sum x^2 (and sum x for even n).
+    """
+    if n == 1:
+        root, sign, powers = 0, 0, 0
+    elif n == 2:
+        root, sign, powers = TRANS_SLOTS, 1, 0
+    else:
+        root, sign = 2 * TRANS_SLOTS + 1, 1
+        powers = {3: 0, 4: 1, 5: 1, 6: 2, 7: 2, 8: 3}[n]
+    accum = n + ((1 + (n % 2 == 0)) if cf else 0)
+    return root + sign + powers + accum
+
+
+def pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
+    """Slots per output pixel: microphone loop + Newton-Girard + CF + envelope FIR."""
+    ng = {1: 0, 2: 3, 3: 7, 4: 11, 5: 15, 6: 21, 7: 28, 8: 36}[n]
+    cf_ops = (4 + TRANS_SLOTS) if cf else 0      # square, fma, rcp, 2 mul
+    return M * mic_slots(n, cf) + ng + cf_ops + 1 + fir_len
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_09165_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches this kernel."""
+    path = os.path.join(ROOT, "profiles", "dmas_envelope_order5_erti32_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source") != kernel_source_hash() or rec.get("workload") != workload_key:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(frame, taps, stride: int = 4):
+    """Time the FP64 oracle on every ``stride``-th direction of the same frame (rows + envelope)."""
+    import oracle
+    rows = list(range(0, frame.num_dirs, stride))
+    x64 = frame.x_f32().astype(np.float64)
+    t0 = time.perf_counter()
+    y = oracle.frame_rows(frame, x=x64, rows=rows)
+    oracle.envelope(y, taps.astype(np.float64))
+    dt = time.perf_counter() - t0
+    pix = len(rows) * frame.num_samples
+    return {"value": pix / dt, "unit": "direction*samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(rows)} of {frame.num_dirs} directions (every {stride}th) x {frame.num_samples} "
+                      f"samples, order-5 DMAS+CF+envelope, FP64, {dt:.2f} s wall"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="also time RF output, CF off and FP64 Newton-Girard")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB, --steps times (HBM counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the beamformer shards by direction with no communication, and this "
+              "build runs on a single MI355X; use --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import synth
+    from paper_2511_09165_amd import load_library, plan_for_frame
+
+    load_library()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": args.steps}), flush=True)
+        return 0
+    frame = synth.config2()
+    M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
+    fir_len = 63
+    plan = plan_for_frame(frame, fir_len=fir_len)
+    taps = None
+    try:
+        import oracle
+        taps = oracle.lowpass_taps(fir_len, 5000.0, frame.fs)
+    except Exception:
+        taps = None
+    x = torch.from_numpy(frame.x_f32()).cuda()
+    out = torch.empty((D, T), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.envelope(x, out=out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.envelope(x, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    pixels = D * T
+    value = pixels / (ms_per_step * 1e-3)
+
+    slots = pixel_slots(M, n, True, fir_len) * pixels
+    achieved = slots / (kernel_ms * 1e-3)
+    workload_key = f"config2 M={M} D={D} T={T} n={n} cf=1 env L={fir_len}"
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12,
+                "unit": "TOP/s", "frac": achieved / VALU_SLOTS_PER_S, "traffic": measured_traffic(workload_key),
+                "kernel_ms": kernel_ms, "ops_per_pixel": pixel_slots(M, n, True, fir_len),
+                "op": "VALU lane-instruction issue slot (transcendental = 2)"}
+
+    extra = {}
+    if args.extra:
+        def timeit(fn, reps=max(5, args.steps // 2)):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+        extra["rf_ms"] = timeit(lambda: plan.beamform(x, out=out))
+        with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
+            extra["no_cf_env_ms"] = timeit(lambda: p2.envelope(x, out=out))
+        with plan_for_frame(frame, fir_len=fir_len, ng_fp64=True) as p3:
+            extra["ng_fp64_env_ms"] = timeit(lambda: p3.envelope(x, out=out))
+        extra["plan"] = plan.info()
+
+    cpu = None
+    if not args.no_cpu_baseline and taps is not None:
+        cpu = cpu_baseline(frame, taps)
+
+    rec = {
+        "metric": "direction*samples/sec, order-5 DMAS+CF, 32 mics",
+        "value": value,
+        "unit": "direction*samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded eRTIS-like pulse-echo frame)",
+        "config": {"workload": "eRTIS-like frame: order-5 DMAS+CF+envelope, M=32 mics (12 cm sparse disc), "
+                               "91x46 az/el directions, T=16384 samples at 450 kHz, 63-tap envelope FIR",
+                   "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        rec["extra"] = extra
+    plan.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

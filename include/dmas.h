@@ -1,0 +1,168 @@
+/*
+ * dmas.h -- C ABI of the MI355X (gfx950) DMAS-CF beamforming library.
+ *
+ * The library evaluates n-th order Delay-Multiply-and-Sum beamforming with
+ * optional Coherence-Factor weighting and envelope detection, following
+ * W. Jansen, W. Daems, J. Steckel, "Delay-Multiply-And-Sum Beamforming for
+ * Real-Time In-Air Acoustic Imaging":
+ *   - problem statement and pre-steering, Section II, eq. (1);
+ *   - signed n-th root, eq. (4); DMAS-n as the n-th elementary symmetric
+ *     polynomial of the roots, eqs. (5)/(6);
+ *   - evaluation through the power sums of eq. (7) and the Newton-Girard
+ *     identities, eqs. (8)-(12), in O(M) per output pixel;
+ *   - coherence factor, eqs. (13)/(14);
+ *   - envelope detection (|.| then low-pass filter), the pipeline of Section II.
+ *
+ * Conventions (M microphones, D directions or voxels, T samples per channel):
+ *   - Recordings d_x: device memory, M x T row-major (channel i starts at
+ *     element i*T), element type given by the plan's in_dtype.
+ *   - Images d_y / d_env: device memory, D x T row-major FP32;
+ *     element [p*T + t] is the output for direction p at sample t (the same
+ *     time index as the input).
+ *   - Steering delay (eq. (1)): x_i(t, p) = m_i(t + tau_{i,p}) with
+ *       far field : tau = -(r_i . u_p) / c      (u_p unit vector toward the source)
+ *       near field: tau = (|v_p - r_i| - |v_p|) / c   (v_p voxel centre)
+ *     computed on the device in FP64 for every (direction, microphone). The
+ *     NEAREST mode uses floor(fs*tau + 1/2) whole samples; the LINEAR mode
+ *     interpolates between floor(fs*tau) and floor(fs*tau) + 1.
+ *     Samples outside [0, T) are zero.
+ *   - Signed root: sgn(0) = 0. Channel values below the FP32 normal range
+ *     (|x| < 2^-126) enter the root as zero.
+ *   - Coherence factor: CF = (sum x_i)^2 / (M * sum x_i^2 + cf_eps) on the
+ *     delayed samples; y = E_n * CF.
+ *   - Envelope: env[t] = sum_k h[k] * |y[t + (L-1)/2 - k]|, y = 0 outside
+ *     [0, T), odd L.
+ *   - in_scale multiplies the result (S is homogeneous of degree 1 in x for a
+ *     positive scale); it lets FP16/BF16 storage carry a per-frame scale.
+ *
+ * Ownership and threading:
+ *   - A plan owns device copies of the geometry, taps and tiling tables; it is
+ *     immutable after creation and may be used from several host threads and
+ *     streams at once. The caller owns every I/O buffer and must make sure
+ *     no work using a plan is in flight when it destroys the plan.
+ *   - A plan is bound to the device that was current when it was created;
+ *     calls must be made with that device current.
+ *   - Launch functions are asynchronous on the given stream (a hipStream_t
+ *     passed as void*; NULL is the default stream). They return after the
+ *     launch, not after completion.
+ *
+ * Errors: every call returns a dmas_status_t. Argument and shape checks are
+ * made on the host before anything is launched; a failed check launches
+ * nothing. dmas_last_error() returns a message for the calling thread's most
+ * recent failure. Data values are not checked: NaN and Inf propagate.
+ */
+#ifndef DMAS_H
+#define DMAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmas_plan_s *dmas_plan_t;
+
+typedef enum {
+    DMAS_OK = 0,
+    DMAS_ERR_INVALID_ARG = 1,   /* bad pointer, size, order or flag */
+    DMAS_ERR_UNSUPPORTED = 2,   /* valid request this build does not serve */
+    DMAS_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+    DMAS_ERR_DEVICE = 4         /* a HIP call or kernel launch failed */
+} dmas_status_t;
+
+typedef enum { DMAS_FARFIELD = 0, DMAS_NEARFIELD = 1 } dmas_geometry_t;
+typedef enum { DMAS_F32 = 0, DMAS_F16 = 1, DMAS_BF16 = 2 } dmas_dtype_t;
+typedef enum { DMAS_DELAY_NEAREST = 0, DMAS_DELAY_LINEAR = 1 } dmas_delay_mode_t;
+
+/* Largest supported order n and envelope length L. */
+#define DMAS_MAX_ORDER 8
+#define DMAS_MAX_FIR_LEN 255
+
+/*
+ * Plan description. Initialise with dmas_plan_desc_init() and then set the
+ * fields that differ from the defaults. Host pointers are read during
+ * dmas_plan_create() only.
+ */
+typedef struct {
+    int32_t num_mics;      /* M >= 1 */
+    int32_t num_samples;   /* T >= 1 */
+    int32_t num_dirs;      /* D >= 1 */
+    int32_t order;         /* n, 1 <= n <= min(M, DMAS_MAX_ORDER); eq. (5) */
+    int32_t use_cf;        /* 0/1: coherence-factor weighting, eqs. (13)/(14) */
+    int32_t geometry;      /* dmas_geometry_t */
+    const double *mic_pos; /* host, M x 3 metres (x, y, z) */
+    const double *dirs;    /* host, D x 3: unit vectors (far) or voxel centres in metres (near) */
+    double fs;             /* sample rate, Hz, > 0 */
+    double c;              /* speed of sound, m/s; 0 selects 343 */
+    double cf_eps;         /* CF denominator guard; 0 selects 1e-20 */
+    const float *fir_taps; /* host, fir_len taps; NULL selects the default low-pass */
+    int32_t fir_len;       /* odd, 1..DMAS_MAX_FIR_LEN; 0 selects 63 */
+    double fir_fc;         /* default low-pass cut-off in Hz; 0 selects 5000 */
+    int32_t in_dtype;      /* dmas_dtype_t of d_x */
+    int32_t ng_fp64;       /* 0/1: evaluate eqs. (8)-(12) in FP64 instead of FP32 */
+    int32_t compensated;   /* 0/1: compensated (Kahan) FP32 accumulation of the power sums */
+    int32_t delay_mode;    /* dmas_delay_mode_t */
+} dmas_plan_desc_t;
+
+/* Read-only facts about a created plan (tiling chosen for the device). */
+typedef struct {
+    int32_t num_mics, num_samples, num_dirs, order;
+    int32_t dirs_per_tile;     /* directions sharing one staged channel window */
+    int32_t num_tiles;
+    int32_t samples_per_lane;  /* output samples each lane produces per chunk */
+    int32_t chunk;             /* samples per direction per chunk */
+    int32_t segment;           /* samples per direction per workgroup */
+    int32_t num_segments;
+    int32_t window_halo;       /* max |delay difference| to the tile's reference direction */
+    int32_t mics_per_block;    /* microphones staged in LDS at once */
+    int32_t lds_bytes;         /* dynamic LDS per workgroup */
+    int32_t fir_len;
+    int64_t workgroups;        /* per launch */
+} dmas_plan_info_t;
+
+/* Fill *desc with defaults: far field, FP32 input, CF on, nearest delays,
+ * c = 343 m/s, cf_eps = 1e-20, default 63-tap 5 kHz low-pass. */
+dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *desc);
+
+/* Validate *desc, copy geometry and taps to the current device, choose the
+ * tiling. On success *out receives the plan. n > M, an even fir_len and a
+ * non-unit far-field direction (| |u| - 1 | > 1e-6) are DMAS_ERR_INVALID_ARG. */
+dmas_status_t dmas_plan_create(const dmas_plan_desc_t *desc, dmas_plan_t *out);
+
+/* Release a plan. NULL is a no-op. */
+dmas_status_t dmas_plan_destroy(dmas_plan_t plan);
+
+dmas_status_t dmas_plan_query(dmas_plan_t plan, dmas_plan_info_t *info);
+
+/* DMAS-n (+CF) image, eqs. (1)-(14): writes d_y (D x T FP32, device). */
+dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y,
+                            float in_scale, void *stream);
+
+/* DMAS-n (+CF) image followed by envelope detection in the same kernel:
+ * writes d_env (D x T FP32, device). */
+dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env,
+                            float in_scale, void *stream);
+
+/* The steering delays the beamformer uses, eq. (1), computed by the same
+ * device code: d_whole (D x M int32, device) receives floor(fs*tau + 1/2) in
+ * NEAREST mode and floor(fs*tau) in LINEAR mode; d_frac (D x M FP32, device,
+ * may be NULL) receives fs*tau - floor(fs*tau) in LINEAR mode and 0 otherwise. */
+dmas_status_t dmas_steering_delays(dmas_plan_t plan, int32_t *d_whole, float *d_frac,
+                                   void *stream);
+
+/* Default envelope low-pass design (host only): Hamming-windowed sinc of
+ * odd length L and cut-off fc at sample rate fs, unit DC gain. */
+dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *taps);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char *dmas_last_error(void);
+
+/* Library version string. */
+const char *dmas_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMAS_H */

@@ -1,0 +1,678 @@
+// Host implementation of the C ABI declared in include/dmas.h, plus the two
+// small device kernels it needs (steering-delay table and per-tile delay
+// spread). The beamforming kernels live in dmas_kernel.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dmas.h"
+#include "dmas_internal.hpp"
+#include "dmas_kernel.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dmas_status_t fail(dmas_status_t st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    if (std::getenv("DMAS_LOG")) fprintf(stderr, "[dmas] %s\n", buf);
+    return st;
+}
+
+dmas_status_t hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? DMAS_ERR_OUT_OF_MEMORY : DMAS_ERR_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+bool finite_all(const double *v, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// 10-bit-per-axis Morton key of a point scaled into [0, 1]^3.
+uint32_t spread_bits(uint32_t v)
+{
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ff;
+    v = (v | (v << 8)) & 0x0300f00f;
+    v = (v | (v << 4)) & 0x030c30c3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
+}  // namespace
+
+struct dmas_plan_s {
+    int device = 0;
+    int M = 0, T = 0, D = 0, order = 0;
+    bool cf = true, nearfield = false, linear = false, compensated = false;
+    int ng_fp64 = 0;
+    int dtype = DMAS_F32;
+    double fs = 0, c = 0;
+    float cf_eps = 0;
+    int fir_len = 0;
+    int num_tiles = 0;
+    int halo = 0;
+    int mic_block = 0;
+    int row = 0;
+    int seg_rf = 0, seg_env = 0;
+    int nseg_rf = 0, nseg_env = 0;
+    size_t lds_rf = 0, lds_env = 0;
+    int occ_rf = 0, occ_env = 0;
+    double *d_mic = nullptr;
+    double *d_dirs = nullptr;
+    int32_t *d_tiles = nullptr;
+    float *d_taps = nullptr;
+};
+
+namespace {
+
+// Per-tile maximum |whole delay - reference whole delay| over all microphones.
+template <bool NEAR, bool LINEAR>
+__global__ void __launch_bounds__(dmas::kDirsPerTile * dmas::kWaveSize)
+tile_spread_kernel(const double *__restrict__ mic, const double *__restrict__ dirs,
+                   const int32_t *__restrict__ tiles, int M, double fs, double c,
+                   int32_t *__restrict__ out)
+{
+    constexpr int W = dmas::kDirsPerTile;
+    __shared__ int wave_max[W];
+    const int lane = threadIdx.x % dmas::kWaveSize;
+    const int wave = threadIdx.x / dmas::kWaveSize;
+    const int dir = tiles[blockIdx.x * W + wave];
+    const int dir0 = tiles[blockIdx.x * W];
+    int m = 0;
+    if (dir >= 0) {
+        for (int i = lane; i < M; i += dmas::kWaveSize) {
+            float f;
+            const int d0 = dmas::steer_whole<NEAR, LINEAR>(mic + 3 * i, dirs + 3 * dir0, fs, c, &f);
+            const int dw = dmas::steer_whole<NEAR, LINEAR>(mic + 3 * i, dirs + 3 * dir, fs, c, &f);
+            m = max(m, abs(dw - d0));
+        }
+    }
+    for (int s = dmas::kWaveSize / 2; s > 0; s >>= 1) m = max(m, __shfl_xor(m, s));
+    if (lane == 0) wave_max[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int w = 0; w < W; ++w) r = max(r, wave_max[w]);
+        out[blockIdx.x] = r;
+    }
+}
+
+template <bool NEAR, bool LINEAR>
+__global__ void delay_table_kernel(const double *__restrict__ mic, const double *__restrict__ dirs,
+                                   int M, int D, double fs, double c, int32_t *__restrict__ whole,
+                                   float *__restrict__ frac)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)M * D) return;
+    const int p = (int)(idx / M);
+    const int i = (int)(idx % M);
+    float f;
+    whole[idx] = dmas::steer_whole<NEAR, LINEAR>(mic + 3 * i, dirs + 3 * p, fs, c, &f);
+    if (frac) frac[idx] = f;
+}
+
+void design_lowpass(int L, double fc, double fs, std::vector<double> &h)
+{
+    const double pi = 3.14159265358979323846;
+    const int half = (L - 1) / 2;
+    const double wc = 2.0 * fc / fs;
+    h.assign(L, 0.0);
+    double sum = 0.0;
+    for (int k = 0; k < L; ++k) {
+        const double m = k - half;
+        const double ideal = (m == 0.0) ? wc : std::sin(pi * wc * m) / (pi * m);
+        const double w = (L == 1) ? 1.0 : 0.54 - 0.46 * std::cos(2.0 * pi * k / (L - 1));
+        h[k] = ideal * w;
+        sum += h[k];
+    }
+    for (double &v : h) v /= sum;
+}
+
+void plan_free(dmas_plan_s *p)
+{
+    if (!p) return;
+    int cur = 0;
+    bool switched = false;
+    if (hipGetDevice(&cur) == hipSuccess && cur != p->device) switched = hipSetDevice(p->device) == hipSuccess;
+    hipFree(p->d_mic);
+    hipFree(p->d_dirs);
+    hipFree(p->d_tiles);
+    hipFree(p->d_taps);
+    if (switched) hipSetDevice(cur);
+    delete p;
+}
+
+// Output samples per workgroup. Every segment is a multiple of 32 samples
+// (aligned output lines) and, with the envelope halo, a whole number of
+// chunks. The count is chosen to minimise (workgroup rounds on the device) x
+// (chunks per workgroup): long segments waste little halo, but the last round
+// of workgroups should not leave most CUs idle.
+void choose_segments(int T, int num_tiles, int extra, int64_t slots, int fixed, int *seg, int *nseg)
+{
+    const int C = dmas::kChunk;
+    auto shape = [&](int want, int *s_out, int *n_out, int *chunks_out) {
+        int s = (T + want - 1) / want;
+        s = (s + 31) & ~31;
+        const int chunks = (s + extra + C - 1) / C;
+        s = std::max(32, (chunks * C - extra) & ~31);
+        *s_out = s;
+        *n_out = (T + s - 1) / s;
+        *chunks_out = (s + extra + C - 1) / C;
+    };
+    if (fixed > 0) {
+        *seg = (fixed + 31) & ~31;
+        *nseg = (T + *seg - 1) / *seg;
+        return;
+    }
+    double best = 0;
+    const int max_seg = std::max(1, (T + 31) / 32);
+    for (int want = 1; want <= max_seg; ++want) {
+        int s, nsg, chunks;
+        shape(want, &s, &nsg, &chunks);
+        const int64_t wgs = (int64_t)num_tiles * nsg;
+        const double rounds = (double)((wgs + slots - 1) / slots);
+        const double cost = rounds * chunks;
+        if (want == 1 || cost < best * (1.0 - 1e-9)) {
+            best = cost;
+            *seg = s;
+            *nseg = nsg;
+        }
+        if (wgs > 64 * slots) break;
+    }
+}
+
+// Host estimate of fs*tau (tiling heuristics only; the kernels compute their own).
+double host_steer(const double *r, const double *v, bool nearfield, double fs, double c)
+{
+    if (!nearfield) return -fs * (r[0] * v[0] + r[1] * v[1] + r[2] * v[2]) / c;
+    const double dm = std::sqrt((v[0] - r[0]) * (v[0] - r[0]) + (v[1] - r[1]) * (v[1] - r[1]) +
+                                (v[2] - r[2]) * (v[2] - r[2]));
+    return fs * (dm - std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2])) / c;
+}
+
+// Microphones that bound the delay spread: the extremes of the array along
+// 13 axes, plus the one farthest from the centroid.
+std::vector<int> probe_mics(const double *mic, int M)
+{
+    static const double axes[13][3] = {{1, 0, 0},  {0, 1, 0},  {0, 0, 1},  {1, 1, 0},  {1, -1, 0},
+                                       {1, 0, 1},  {1, 0, -1}, {0, 1, 1},  {0, 1, -1}, {1, 1, 1},
+                                       {1, 1, -1}, {1, -1, 1}, {-1, 1, 1}};
+    std::vector<int> out;
+    auto add = [&](int i) {
+        if (std::find(out.begin(), out.end(), i) == out.end()) out.push_back(i);
+    };
+    double cen[3] = {0, 0, 0};
+    for (int i = 0; i < M; ++i)
+        for (int a = 0; a < 3; ++a) cen[a] += mic[3 * i + a] / M;
+    for (const auto &ax : axes) {
+        int lo = 0, hi = 0;
+        double vlo = INFINITY, vhi = -INFINITY;
+        for (int i = 0; i < M; ++i) {
+            const double d = mic[3 * i] * ax[0] + mic[3 * i + 1] * ax[1] + mic[3 * i + 2] * ax[2];
+            if (d < vlo) vlo = d, lo = i;
+            if (d > vhi) vhi = d, hi = i;
+        }
+        add(lo);
+        add(hi);
+    }
+    int far = 0;
+    double dfar = -1;
+    for (int i = 0; i < M; ++i) {
+        double d = 0;
+        for (int a = 0; a < 3; ++a) d += (mic[3 * i + a] - cen[a]) * (mic[3 * i + a] - cen[a]);
+        if (d > dfar) dfar = d, far = i;
+    }
+    add(far);
+    return out;
+}
+
+// Group directions into tiles of up to kDirsPerTile whose steering delays stay
+// close to the tile's first (reference) direction: walk the directions along a
+// Morton curve and greedily add, from a short look-ahead window, those within
+// a delay budget of the reference. The budget adapts to the grid (twice the
+// median spread of plain consecutive groups); it only affects efficiency, the
+// exact spread is measured on the device afterwards.
+std::vector<int32_t> make_tiles(const dmas_plan_desc_t *d, bool nearfield, double c)
+{
+    constexpr int W = dmas::kDirsPerTile;
+    const int D = d->num_dirs;
+    std::vector<int> order(D);
+    std::iota(order.begin(), order.end(), 0);
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int q = 0; q < D; ++q)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], d->dirs[3 * q + a]);
+            hi[a] = std::max(hi[a], d->dirs[3 * q + a]);
+        }
+    std::vector<uint32_t> key(D);
+    for (int q = 0; q < D; ++q) {
+        uint32_t k = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double span = hi[a] - lo[a];
+            const double u = span > 0 ? (d->dirs[3 * q + a] - lo[a]) / span : 0.0;
+            k |= spread_bits((uint32_t)std::min(1023.0, std::floor(u * 1024.0))) << a;
+        }
+        key[q] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+
+    const std::vector<int> probes = probe_mics(d->mic_pos, d->num_mics);
+    const int P = (int)probes.size();
+    std::vector<double> tau((size_t)D * P);
+    for (int q = 0; q < D; ++q)
+        for (int j = 0; j < P; ++j)
+            tau[(size_t)q * P + j] = host_steer(d->mic_pos + 3 * probes[j], d->dirs + 3 * q, nearfield, d->fs, c);
+    auto dist = [&](int a, int b) {
+        double m = 0;
+        for (int j = 0; j < P; ++j) m = std::max(m, std::fabs(tau[(size_t)a * P + j] - tau[(size_t)b * P + j]));
+        return m;
+    };
+    std::vector<double> natural;
+    for (int q = 0; q < D; q += W) {
+        double m = 0;
+        for (int w = 1; w < W && q + w < D; ++w) m = std::max(m, dist(order[q], order[q + w]));
+        natural.push_back(m);
+    }
+    std::nth_element(natural.begin(), natural.begin() + natural.size() / 2, natural.end());
+    const double budget = std::max(6.0, 2.0 * natural[natural.size() / 2] + 1.0);
+
+    std::vector<int32_t> tiles;
+    std::vector<char> used(D, 0);
+    const int lookahead = 4 * W;
+    for (int pos = 0; pos < D; ++pos) {
+        if (used[pos]) continue;
+        const int ref = order[pos];
+        used[pos] = 1;
+        int32_t tile[W];
+        int cnt = 0;
+        tile[cnt++] = ref;
+        for (int j = pos + 1; j < D && j <= pos + lookahead && cnt < W; ++j) {
+            if (used[j]) continue;
+            if (dist(ref, order[j]) <= budget) {
+                tile[cnt++] = order[j];
+                used[j] = 1;
+            }
+        }
+        for (int w = 0; w < W; ++w) tiles.push_back(w < cnt ? tile[w] : -1);
+    }
+    return tiles;
+}
+
+hipError_t launch_dmas(int order, const dmas::KernelParams *kp, const dmas::LaunchShape &ls, hipStream_t st,
+                       int *blocks = nullptr)
+{
+    switch (order) {
+    case 1: return dmas::launch_order1(kp, ls, st, blocks);
+    case 2: return dmas::launch_order2(kp, ls, st, blocks);
+    case 3: return dmas::launch_order3(kp, ls, st, blocks);
+    case 4: return dmas::launch_order4(kp, ls, st, blocks);
+    case 5: return dmas::launch_order5(kp, ls, st, blocks);
+    case 6: return dmas::launch_order6(kp, ls, st, blocks);
+    case 7: return dmas::launch_order7(kp, ls, st, blocks);
+    case 8: return dmas::launch_order8(kp, ls, st, blocks);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+dmas::LaunchShape shape_of(const dmas_plan_s *p, bool env)
+{
+    dmas::LaunchShape ls{};
+    ls.order = p->order;
+    ls.cf = p->cf;
+    ls.env = env;
+    ls.nearfield = p->nearfield;
+    ls.linear = p->linear;
+    ls.compensated = p->compensated;
+    ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
+    ls.lds_bytes = env ? p->lds_env : p->lds_rf;
+    return ls;
+}
+
+dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scale, void *stream,
+                  bool env)
+{
+    if (!plan) return fail(DMAS_ERR_INVALID_ARG, "plan is NULL");
+    if (!d_x || !d_out) return fail(DMAS_ERR_INVALID_ARG, "device pointer is NULL");
+    if (!(in_scale > 0.0f) || !std::isfinite(in_scale))
+        return fail(DMAS_ERR_INVALID_ARG, "in_scale must be finite and > 0 (got %g)", (double)in_scale);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != plan->device)
+        return fail(DMAS_ERR_INVALID_ARG, "plan belongs to device %d but device %d is current", plan->device,
+                    cur);
+    dmas::KernelParams kp{};
+    kp.x = d_x;
+    kp.out = d_out;
+    kp.mic = plan->d_mic;
+    kp.dirs = plan->d_dirs;
+    kp.tile_dirs = plan->d_tiles;
+    kp.taps = plan->d_taps;
+    kp.M = plan->M;
+    kp.T = plan->T;
+    kp.D = plan->D;
+    kp.fir_len = env ? plan->fir_len : 1;
+    kp.num_tiles = plan->num_tiles;
+    kp.seg_len = env ? plan->seg_env : plan->seg_rf;
+    kp.halo = plan->halo;
+    kp.row = plan->row;
+    kp.mic_block = plan->mic_block;
+    kp.dtype = plan->dtype;
+    kp.ng_fp64 = plan->ng_fp64;
+    kp.fs = plan->fs;
+    kp.c = plan->c;
+    kp.cf_eps = plan->cf_eps;
+    kp.in_scale = in_scale;
+    const dmas::LaunchShape ls = shape_of(plan, env);
+    hipError_t e = launch_dmas(plan->order, &kp, ls, static_cast<hipStream_t>(stream));
+    if (e == hipErrorNotSupported)
+        return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d linear=%d comp=%d",
+                    plan->order, (int)plan->cf, (int)env, (int)plan->nearfield, (int)plan->linear,
+                    (int)plan->compensated);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DMAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *d)
+{
+    if (!d) return fail(DMAS_ERR_INVALID_ARG, "desc is NULL");
+    std::memset(d, 0, sizeof *d);
+    d->order = 1;
+    d->use_cf = 1;
+    d->geometry = DMAS_FARFIELD;
+    d->c = 343.0;
+    d->cf_eps = 1e-20;
+    d->fir_len = 63;
+    d->fir_fc = 5000.0;
+    d->in_dtype = DMAS_F32;
+    d->delay_mode = DMAS_DELAY_NEAREST;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
+{
+    if (!d || !out) return fail(DMAS_ERR_INVALID_ARG, "desc or out is NULL");
+    *out = nullptr;
+    const int M = d->num_mics, T = d->num_samples, D = d->num_dirs, n = d->order;
+    if (M < 1 || T < 1 || D < 1)
+        return fail(DMAS_ERR_INVALID_ARG, "sizes must be >= 1 (M=%d T=%d D=%d)", M, T, D);
+    if (n < 1 || n > DMAS_MAX_ORDER) return fail(DMAS_ERR_INVALID_ARG, "order %d outside 1..%d", n, DMAS_MAX_ORDER);
+    if (n > M) return fail(DMAS_ERR_INVALID_ARG, "order %d exceeds the number of microphones %d", n, M);
+    if ((int64_t)T + 2 * DMAS_MAX_FIR_LEN + 4 * dmas::kChunk > INT32_MAX / 2)
+        return fail(DMAS_ERR_INVALID_ARG, "num_samples %d too large", T);
+    if (!d->mic_pos || !d->dirs) return fail(DMAS_ERR_INVALID_ARG, "mic_pos or dirs is NULL");
+    if (d->use_cf != 0 && d->use_cf != 1) return fail(DMAS_ERR_INVALID_ARG, "use_cf must be 0 or 1");
+    if (d->geometry != DMAS_FARFIELD && d->geometry != DMAS_NEARFIELD)
+        return fail(DMAS_ERR_INVALID_ARG, "unknown geometry %d", d->geometry);
+    if (d->in_dtype != DMAS_F32 && d->in_dtype != DMAS_F16 && d->in_dtype != DMAS_BF16)
+        return fail(DMAS_ERR_INVALID_ARG, "unknown in_dtype %d", d->in_dtype);
+    if (d->delay_mode != DMAS_DELAY_NEAREST && d->delay_mode != DMAS_DELAY_LINEAR)
+        return fail(DMAS_ERR_INVALID_ARG, "unknown delay_mode %d", d->delay_mode);
+    if ((d->ng_fp64 != 0 && d->ng_fp64 != 1) || (d->compensated != 0 && d->compensated != 1))
+        return fail(DMAS_ERR_INVALID_ARG, "ng_fp64 and compensated must be 0 or 1");
+    if (!(d->fs > 0.0) || !std::isfinite(d->fs)) return fail(DMAS_ERR_INVALID_ARG, "fs must be > 0");
+    const double c = d->c == 0.0 ? 343.0 : d->c;
+    if (!(c > 0.0) || !std::isfinite(c)) return fail(DMAS_ERR_INVALID_ARG, "c must be > 0");
+    const double eps = d->cf_eps == 0.0 ? 1e-20 : d->cf_eps;
+    if (!(eps > 0.0) || !std::isfinite(eps) || eps < 1.1754944e-38)
+        return fail(DMAS_ERR_INVALID_ARG, "cf_eps must be a positive normal FP32 value");
+    const int L = d->fir_len == 0 ? 63 : d->fir_len;
+    if (L < 1 || L > DMAS_MAX_FIR_LEN || (L % 2) == 0)
+        return fail(DMAS_ERR_INVALID_ARG, "fir_len %d must be odd in 1..%d", L, DMAS_MAX_FIR_LEN);
+    const double fc = d->fir_fc == 0.0 ? 5000.0 : d->fir_fc;
+    if (!d->fir_taps && !(fc > 0.0 && fc < 0.5 * d->fs))
+        return fail(DMAS_ERR_INVALID_ARG, "fir_fc must lie in (0, fs/2)");
+    if (!finite_all(d->mic_pos, 3 * (size_t)M) || !finite_all(d->dirs, 3 * (size_t)D))
+        return fail(DMAS_ERR_INVALID_ARG, "geometry contains NaN or Inf");
+    if (d->geometry == DMAS_FARFIELD) {
+        for (int p = 0; p < D; ++p) {
+            const double *u = d->dirs + 3 * p;
+            const double nrm = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (std::fabs(nrm - 1.0) > 1e-6)
+                return fail(DMAS_ERR_INVALID_ARG, "far-field direction %d is not a unit vector (|u| = %.9g)", p, nrm);
+        }
+    }
+    if (d->compensated && (d->geometry != DMAS_FARFIELD || !d->use_cf))
+        return fail(DMAS_ERR_UNSUPPORTED, "compensated accumulation is built for far field with CF only");
+    if (d->delay_mode == DMAS_DELAY_LINEAR && !d->use_cf)
+        return fail(DMAS_ERR_UNSUPPORTED, "linear delays are built with CF only");
+    if (d->delay_mode == DMAS_DELAY_LINEAR && d->compensated)
+        return fail(DMAS_ERR_UNSUPPORTED, "linear delays with compensated sums are not built");
+    if (d->fir_taps) {
+        for (int k = 0; k < L; ++k)
+            if (!std::isfinite(d->fir_taps[k])) return fail(DMAS_ERR_INVALID_ARG, "fir_taps contain NaN or Inf");
+    }
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+
+    dmas_plan_s *p = new (std::nothrow) dmas_plan_s();
+    if (!p) return fail(DMAS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->device = dev;
+    p->M = M;
+    p->T = T;
+    p->D = D;
+    p->order = n;
+    p->cf = d->use_cf != 0;
+    p->nearfield = d->geometry == DMAS_NEARFIELD;
+    p->linear = d->delay_mode == DMAS_DELAY_LINEAR;
+    p->compensated = d->compensated != 0;
+    p->ng_fp64 = d->ng_fp64;
+    p->dtype = d->in_dtype;
+    p->fs = d->fs;
+    p->c = c;
+    p->cf_eps = (float)eps;
+    p->fir_len = L;
+
+    // ---- tiles of nearby directions (Morton order, greedy within a delay budget) ----
+    constexpr int W = dmas::kDirsPerTile;
+    std::vector<int32_t> tiles = make_tiles(d, p->nearfield, c);
+    p->num_tiles = (int)(tiles.size() / W);
+
+    std::vector<double> taps_d;
+    std::vector<float> taps((size_t)L);
+    if (d->fir_taps) {
+        std::copy(d->fir_taps, d->fir_taps + L, taps.begin());
+    } else {
+        design_lowpass(L, fc, d->fs, taps_d);
+        for (int k = 0; k < L; ++k) taps[k] = (float)taps_d[k];
+    }
+
+    auto dev_copy = [&](void **dst, const void *src, size_t bytes, const char *what) -> dmas_status_t {
+        hipError_t err = hipMalloc(dst, bytes);
+        if (err != hipSuccess) return hip_fail(err, what);
+        err = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (err != hipSuccess) return hip_fail(err, what);
+        return DMAS_OK;
+    };
+    dmas_status_t st;
+    if ((st = dev_copy((void **)&p->d_mic, d->mic_pos, sizeof(double) * 3 * M, "mic_pos")) != DMAS_OK ||
+        (st = dev_copy((void **)&p->d_dirs, d->dirs, sizeof(double) * 3 * (size_t)D, "dirs")) != DMAS_OK ||
+        (st = dev_copy((void **)&p->d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(), "tiles")) != DMAS_OK ||
+        (st = dev_copy((void **)&p->d_taps, taps.data(), sizeof(float) * L, "taps")) != DMAS_OK) {
+        plan_free(p);
+        return st;
+    }
+
+    // ---- delay spread per tile, measured with the kernels' own delay code ----
+    {
+        int32_t *d_spread = nullptr;
+        e = hipMalloc(&d_spread, sizeof(int32_t) * p->num_tiles);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_fail(e, "spread buffer");
+        }
+        auto kern = p->nearfield ? (p->linear ? tile_spread_kernel<true, true> : tile_spread_kernel<true, false>)
+                                 : (p->linear ? tile_spread_kernel<false, true> : tile_spread_kernel<false, false>);
+        hipLaunchKernelGGL(kern, dim3(p->num_tiles), dim3(W * dmas::kWaveSize), 0, nullptr, p->d_mic, p->d_dirs,
+                           p->d_tiles, M, p->fs, p->c, d_spread);
+        e = hipGetLastError();
+        std::vector<int32_t> spread(p->num_tiles);
+        if (e == hipSuccess)
+            e = hipMemcpy(spread.data(), d_spread, sizeof(int32_t) * p->num_tiles, hipMemcpyDeviceToHost);
+        hipFree(d_spread);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_fail(e, "tile spread");
+        }
+        p->halo = 0;
+        for (int v : spread) p->halo = std::max(p->halo, v);
+    }
+
+    // ---- LDS layout: mic_block x row windows, reference delays, envelope rings ----
+    const int C = dmas::kChunk;
+    const int H = (L - 1) / 2;
+    p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
+    p->row = (p->row + 3) & ~3;
+    const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
+    const size_t ring_bytes = sizeof(float) * (size_t)W * (C + 2 * H);
+    const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
+    int mb = std::min(M, dmas::kMaxMicBlock);
+    while (mb > 1 && fixed + ring_bytes + sizeof(float) * (size_t)mb * p->row > lds_cap) mb /= 2;
+    if (fixed + ring_bytes + sizeof(float) * (size_t)mb * p->row > lds_cap) {
+        plan_free(p);
+        return fail(DMAS_ERR_UNSUPPORTED,
+                    "direction tiles spread over %d samples: the channel window does not fit in LDS", p->halo);
+    }
+    p->mic_block = mb;
+    p->lds_rf = fixed + sizeof(float) * (size_t)mb * p->row;
+    p->lds_env = p->lds_rf + ring_bytes;
+
+    const char *fixed_seg = std::getenv("DMAS_SEGMENT");
+    const int seg_override = fixed_seg ? std::atoi(fixed_seg) : 0;
+    const int extra_env = 2 * H + (32 - (2 * H) % 32) % 32;
+    p->nseg_rf = p->nseg_env = 1;   // shape_of() needs a grid; the occupancy query ignores it
+    for (int env = 0; env < 2; ++env) {
+        int blocks = 0;
+        e = launch_dmas(n, nullptr, shape_of(p, env != 0), nullptr, &blocks);
+        if (e != hipSuccess && e != hipErrorNotSupported) {
+            plan_free(p);
+            return hip_fail(e, "occupancy query");
+        }
+        const int64_t slots = (int64_t)prop.multiProcessorCount * std::max(1, blocks);
+        if (env)
+            choose_segments(T, p->num_tiles, extra_env, slots, seg_override, &p->seg_env, &p->nseg_env);
+        else
+            choose_segments(T, p->num_tiles, 0, slots, seg_override, &p->seg_rf, &p->nseg_rf);
+        if (env) p->occ_env = blocks; else p->occ_rf = blocks;
+    }
+    if ((int64_t)p->num_tiles * std::max(p->nseg_rf, p->nseg_env) > INT32_MAX) {
+        plan_free(p);
+        return fail(DMAS_ERR_UNSUPPORTED, "grid too large");
+    }
+    if (std::getenv("DMAS_LOG"))
+        fprintf(stderr,
+                "[dmas] plan M=%d T=%d D=%d n=%d tiles=%d halo=%d row=%d mb=%d seg=%d/%d nseg=%d/%d lds=%zu/%zu "
+                "occupancy=%d/%d\n",
+                M, T, D, n, p->num_tiles, p->halo, p->row, p->mic_block, p->seg_rf, p->seg_env, p->nseg_rf,
+                p->nseg_env, p->lds_rf, p->lds_env, p->occ_rf, p->occ_env);
+    *out = p;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_plan_destroy(dmas_plan_t plan)
+{
+    plan_free(plan);
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_plan_query(dmas_plan_t p, dmas_plan_info_t *info)
+{
+    if (!p || !info) return fail(DMAS_ERR_INVALID_ARG, "plan or info is NULL");
+    std::memset(info, 0, sizeof *info);
+    info->num_mics = p->M;
+    info->num_samples = p->T;
+    info->num_dirs = p->D;
+    info->order = p->order;
+    info->dirs_per_tile = dmas::kDirsPerTile;
+    info->num_tiles = p->num_tiles;
+    info->samples_per_lane = dmas::kSamplesPerLane;
+    info->chunk = dmas::kChunk;
+    info->segment = p->seg_env;
+    info->num_segments = p->nseg_env;
+    info->window_halo = p->halo;
+    info->mics_per_block = p->mic_block;
+    info->lds_bytes = (int32_t)p->lds_env;
+    info->fir_len = p->fir_len;
+    info->workgroups = (int64_t)p->num_tiles * p->nseg_env;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y, float in_scale, void *stream)
+{
+    return run(plan, d_x, d_y, in_scale, stream, false);
+}
+
+dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env, float in_scale, void *stream)
+{
+    return run(plan, d_x, d_env, in_scale, stream, true);
+}
+
+dmas_status_t dmas_steering_delays(dmas_plan_t p, int32_t *d_whole, float *d_frac, void *stream)
+{
+    if (!p || !d_whole) return fail(DMAS_ERR_INVALID_ARG, "plan or d_whole is NULL");
+    const int64_t n = (int64_t)p->M * p->D;
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    if (blocks > INT32_MAX) return fail(DMAS_ERR_UNSUPPORTED, "delay table too large");
+    auto kern = p->nearfield ? (p->linear ? delay_table_kernel<true, true> : delay_table_kernel<true, false>)
+                             : (p->linear ? delay_table_kernel<false, true> : delay_table_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, static_cast<hipStream_t>(stream), p->d_mic,
+                       p->d_dirs, p->M, p->D, p->fs, p->c, d_whole, d_frac);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "delay table launch");
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_design_lowpass(int32_t L, double fc, double fs, float *taps)
+{
+    if (!taps) return fail(DMAS_ERR_INVALID_ARG, "taps is NULL");
+    if (L < 1 || L > DMAS_MAX_FIR_LEN || (L % 2) == 0)
+        return fail(DMAS_ERR_INVALID_ARG, "fir_len %d must be odd in 1..%d", L, DMAS_MAX_FIR_LEN);
+    if (!(fs > 0.0) || !(fc > 0.0) || !(fc < 0.5 * fs))
+        return fail(DMAS_ERR_INVALID_ARG, "need 0 < fc < fs/2");
+    std::vector<double> h;
+    design_lowpass(L, fc, fs, h);
+    for (int k = 0; k < L; ++k) taps[k] = (float)h[k];
+    return DMAS_OK;
+}
+
+const char *dmas_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+const char *dmas_version(void)
+{
+    return "dmas-mi355x 0.1 (gfx950)";
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Internal interface between the host API (dmas_api.hip) and the kernel
+// instantiation units (dmas_order*.hip). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dmas {
+
+constexpr int kWaveSize = 64;
+constexpr int kMaxOrder = 8;
+constexpr int kMaxMicBlock = 64;   // microphones staged in LDS at once (<= wave size)
+
+// Everything a beamforming launch needs, passed by value as the kernel argument.
+struct KernelParams {
+    const void *x;            // M x T channels (dtype below), device
+    float *out;               // D x T image, device
+    const double *mic;        // M x 3, device
+    const double *dirs;       // D x 3, device
+    const int32_t *tile_dirs; // num_tiles x dirs_per_tile direction indices (-1 = empty), device
+    const float *taps;        // fir_len envelope taps, device
+    int32_t M, T, D;
+    int32_t fir_len;          // odd
+    int32_t num_tiles;
+    int32_t seg_len;          // output samples per direction per workgroup
+    int32_t halo;             // bound on |delay - reference delay| within a tile
+    int32_t row;              // LDS row length per microphone (floats)
+    int32_t mic_block;        // microphones per LDS block, <= kMaxMicBlock
+    int32_t dtype;            // dmas_dtype_t
+    int32_t ng_fp64;          // evaluate Newton-Girard in FP64
+    double fs, c;
+    float cf_eps;
+    float in_scale;
+};
+
+struct LaunchShape {
+    int order;
+    bool cf;
+    bool env;
+    bool nearfield;
+    bool linear;              // linear fractional-delay interpolation
+    bool compensated;         // Kahan accumulation of the power sums
+    unsigned grid;            // workgroups
+    size_t lds_bytes;         // dynamic LDS
+};
+
+// Compile-time tiling shared by host and device: waves (= directions) per
+// workgroup and output samples per lane per chunk.
+constexpr int kDirsPerTile = 8;
+constexpr int kSamplesPerLane = 4;
+constexpr int kChunk = kWaveSize * kSamplesPerLane;
+
+hipError_t launch_order1(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order2(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order3(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order4(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order5(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order6(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order7(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+hipError_t launch_order8(const KernelParams *, const LaunchShape &, hipStream_t, int *);
+
+}  // namespace dmas

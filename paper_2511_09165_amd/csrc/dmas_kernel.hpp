@@ -1,0 +1,485 @@
+// DMAS-n + CF (+ envelope) beamforming kernel for gfx950 (CDNA4, wave64).
+//
+// Method (Jansen, Daems, Steckel, Section II):
+//   x_i(t, p) = m_i(t + tau_{i,p})                      eq. (1)
+//   s_i = sgn(x_i) |x_i|^(1/n)                          eq. (4)
+//   S = E_n(s_1..s_M)                                   eqs. (5)/(6)
+//     = Newton-Girard polynomial of P_k = sum_i s_i^k   eqs. (7)-(12)
+//   y = S * CF,  CF = (sum x)^2 / (M sum x^2 + eps)     eqs. (13)/(14)
+//   env = low-pass(|y|)                                 pipeline step 3
+//
+// Work decomposition (MI355X-first; not the paper's one-thread-per-pixel CUDA
+// design):
+//   * A workgroup owns one tile of kDirsPerTile nearby directions (one wave per
+//     direction) and one time segment. Directions were grouped on the host so
+//     that their steering delays stay within +-halo samples of the tile's first
+//     (reference) direction.
+//   * The segment is walked in chunks of kChunk samples. For each chunk the
+//     workgroup stages, per microphone, one window of the channel
+//     [t0 + d_ref - halo, t0 + d_ref - halo + row) into LDS (zero outside the
+//     record); every wave then reads its own delayed samples from that window
+//     with a wave-uniform offset, so one staged window serves all directions
+//     of the tile. Microphones are staged in blocks of <= 64 when M is large.
+//   * Each lane owns kSamplesPerLane output samples at stride 64 and keeps
+//     their power sums in registers across all microphones; the LDS reads of a
+//     wave are contiguous (conflict-free) and the per-microphone address update
+//     is one scalar offset shared by all samples of the lane.
+//   * The epilogue evaluates Newton-Girard, CF and either stores y, or writes
+//     |y| into a per-wave LDS ring and applies the FIR there; the ring keeps
+//     the last L-1 values between chunks so the envelope never round-trips
+//     through HBM and needs only L-1 samples of halo per segment.
+//   * There is no contraction here, so no MFMA: the bound is VALU issue.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "dmas_internal.hpp"
+
+namespace dmas {
+
+// ---------------------------------------------------------------------------
+// Steering delay, eq. (1), in samples (fs * tau). Written as a fixed sequence
+// of IEEE double operations with contraction disabled, so that the whole-sample
+// rounding is reproducible on any IEEE machine that evaluates the same steps.
+// ---------------------------------------------------------------------------
+template <bool NEAR>
+__device__ __forceinline__ double steer_samples(const double *__restrict__ r,
+                                                const double *__restrict__ v,
+                                                double fs, double c)
+{
+#pragma clang fp contract(off)
+    double tau;
+    if constexpr (!NEAR) {
+        // plane wave from unit vector v reaches r earlier by (r . v)/c
+        double dot = r[0] * v[0];
+        dot = dot + r[1] * v[1];
+        dot = dot + r[2] * v[2];
+        tau = -dot / c;
+    } else {
+        // spherical wave from point v, aligned to its arrival at the origin
+        double dx = v[0] - r[0];
+        double dy = v[1] - r[1];
+        double dz = v[2] - r[2];
+        double q = dx * dx;
+        q = q + dy * dy;
+        q = q + dz * dz;
+        double q0 = v[0] * v[0];
+        q0 = q0 + v[1] * v[1];
+        q0 = q0 + v[2] * v[2];
+        tau = (__builtin_sqrt(q) - __builtin_sqrt(q0)) / c;
+    }
+    return fs * tau;
+}
+
+// Whole-sample part used to address the channel: nearest sample
+// (floor(f + 1/2)) or, for linear interpolation, floor(f) plus the fraction.
+template <bool NEAR, bool LINEAR>
+__device__ __forceinline__ int steer_whole(const double *r, const double *v, double fs,
+                                           double c, float *frac)
+{
+    const double f = steer_samples<NEAR>(r, v, fs, c);
+    if constexpr (LINEAR) {
+        const double q = __builtin_floor(f);
+        *frac = (float)(f - q);
+        return (int)q;
+    } else {
+        *frac = 0.0f;
+        return (int)__builtin_floor(f + 0.5);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Channel sample conversion (storage type -> FP32).
+// ---------------------------------------------------------------------------
+template <int DT>
+__device__ __forceinline__ float load_sample(const void *__restrict__ x, size_t idx)
+{
+    if constexpr (DT == 0) {
+        return static_cast<const float *>(x)[idx];
+    } else if constexpr (DT == 1) {
+        return __half2float(static_cast<const __half *>(x)[idx]);
+    } else {
+        const uint32_t bits = static_cast<const uint16_t *>(x)[idx];
+        return __uint_as_float(bits << 16);
+    }
+}
+
+// One microphone's window [base, base + row) of the channel starting at
+// element chan, converted to FP32, zero outside [0, T).
+template <int DT>
+__device__ __forceinline__ void stage_row(float *__restrict__ dst, const void *__restrict__ x,
+                                          size_t chan, int base, int row, int T, int lane)
+{
+    for (int r = lane; r < row; r += kWaveSize) {
+        const int t = base + r;
+        dst[r] = (t >= 0 && t < T) ? load_sample<DT>(x, chan + (size_t)t) : 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Power-sum accumulators for one output sample.
+//   p[k], k = 1..N-1 : P_k = sum_i s_i^k                        eq. (7)
+//   p[N]             : P_N = sum x (N odd) or sum |x| (N even), exact since
+//                      s^N = x for odd N and |x| for even N
+//   a                : sum x (only needed separately for even N with CF)
+//   b                : sum x^2 (CF only)
+// With COMP, each sum carries a Kahan compensation term.
+// ---------------------------------------------------------------------------
+template <int N, bool CF, bool COMP>
+struct Acc {
+    float p[N + 1];
+    float a, b;
+    float cp[COMP ? N + 1 : 1];
+    float ca, cb;
+
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k <= N; ++k) p[k] = 0.0f;
+        a = b = 0.0f;
+#pragma unroll
+        for (int k = 0; k < (COMP ? N + 1 : 1); ++k) cp[k] = 0.0f;
+        ca = cb = 0.0f;
+    }
+};
+
+template <bool COMP>
+__device__ __forceinline__ void acc_add(float &sum, float &comp, float term)
+{
+    if constexpr (COMP) {
+        const float y = term - comp;
+        const float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    } else {
+        sum += term;
+    }
+}
+
+template <int N, bool CF, bool COMP>
+__device__ __forceinline__ void accumulate(Acc<N, CF, COMP> &acc, float xv)
+{
+    if constexpr (N == 1) {
+        acc_add<COMP>(acc.p[1], acc.cp[COMP ? 1 : 0], xv);
+        if constexpr (CF) acc_add<COMP>(acc.b, acc.cb, xv * xv);
+        return;
+    } else {
+        const float ax = __builtin_fabsf(xv);
+        float r;
+        if constexpr (N == 2) {
+            r = __builtin_amdgcn_sqrtf(ax);
+        } else {
+            // |x|^(1/N) = 2^(log2|x| / N); log2(0) = -inf gives r = 0
+            r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(ax) * (1.0f / (float)N));
+        }
+        float pw[N];                       // pw[k] = s^k, k = 1..N-1
+        pw[1] = __builtin_copysignf(r, xv);
+        if constexpr (N >= 3) pw[2] = r * r;
+#pragma unroll
+        for (int k = 3; k < N; ++k) pw[k] = (k & 1) ? pw[k - 1] * pw[1] : pw[k / 2] * pw[k / 2];
+#pragma unroll
+        for (int k = 1; k < N; ++k) acc_add<COMP>(acc.p[k], acc.cp[COMP ? k : 0], pw[k]);
+        acc_add<COMP>(acc.p[N], acc.cp[COMP ? N : 0], (N & 1) ? xv : ax);
+        if constexpr (CF && !(N & 1)) acc_add<COMP>(acc.a, acc.ca, xv);
+        if constexpr (CF) acc_add<COMP>(acc.b, acc.cb, xv * xv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Newton-Girard: E_n from P_1..P_n. Orders 2..5 use the paper's expansions,
+// eqs. (9)-(12); higher orders use the recursive form of the same identities
+// (k e_k = sum_{i=1..k} (-1)^(i-1) e_{k-i} P_i), equivalent to eq. (8).
+// ---------------------------------------------------------------------------
+template <int N, typename R>
+__device__ __forceinline__ R newton_girard(const R *P)
+{
+    if constexpr (N == 1) {
+        return P[1];
+    } else if constexpr (N == 2) {
+        return R(0.5) * (P[1] * P[1] - P[2]);
+    } else if constexpr (N == 3) {
+        return R(1.0 / 6.0) * (P[1] * P[1] * P[1] + R(2) * P[3] - R(3) * P[1] * P[2]);
+    } else if constexpr (N == 4) {
+        const R q = P[1] * P[1];
+        return R(1.0 / 24.0) *
+               (q * q - R(6) * P[4] + R(3) * P[2] * P[2] - R(6) * P[2] * q + R(8) * P[3] * P[1]);
+    } else if constexpr (N == 5) {
+        const R q = P[1] * P[1];
+        return R(1.0 / 120.0) *
+               (q * q * P[1] - R(10) * P[2] * q * P[1] + R(15) * P[2] * P[2] * P[1] +
+                R(20) * P[3] * q - R(20) * P[3] * P[2] - R(30) * P[1] * P[4] + R(24) * P[5]);
+    } else {
+        R e[N + 1];
+        e[0] = R(1);
+#pragma unroll
+        for (int k = 1; k <= N; ++k) {
+            R s = R(0);
+#pragma unroll
+            for (int i = 1; i <= k; ++i) {
+                const R term = e[k - i] * P[i];
+                s = (i & 1) ? s + term : s - term;
+            }
+            e[k] = s * (R(1) / R(k));
+        }
+        return e[N];
+    }
+}
+
+template <int N, bool CF, bool COMP>
+__device__ __forceinline__ float finish_pixel(const Acc<N, CF, COMP> &acc, const KernelParams &p)
+{
+    float e;
+    if (p.ng_fp64) {
+        double P[N + 1];
+#pragma unroll
+        for (int k = 1; k <= N; ++k) P[k] = (double)acc.p[k] - (COMP ? (double)acc.cp[COMP ? k : 0] : 0.0);
+        e = (float)newton_girard<N, double>(P);
+    } else {
+        float P[N + 1];
+#pragma unroll
+        for (int k = 1; k <= N; ++k) P[k] = COMP ? acc.p[k] - acc.cp[COMP ? k : 0] : acc.p[k];
+        e = newton_girard<N, float>(P);
+    }
+    if constexpr (CF) {
+        float sx = (N & 1) ? acc.p[N] : acc.a;
+        float sb = acc.b;
+        if constexpr (COMP) {
+            sx -= (N & 1) ? acc.cp[COMP ? N : 0] : acc.ca;
+            sb -= acc.cb;
+        }
+        const float den = __builtin_fmaf((float)p.M, sb, p.cf_eps);
+        e = e * (sx * sx) * __builtin_amdgcn_rcpf(den);
+    }
+    return e * p.in_scale;
+}
+
+// ---------------------------------------------------------------------------
+// The kernel.
+// ---------------------------------------------------------------------------
+template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, bool COMP>
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
+dmas_kernel(const KernelParams p)
+{
+    constexpr int W = kDirsPerTile;
+    constexpr int K = kSamplesPerLane;
+    constexpr int C = kChunk;
+    extern __shared__ float smem[];
+
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    const int tile = blockIdx.x % p.num_tiles;   // segment-major: concurrent workgroups share a time window
+    const int seg = blockIdx.x / p.num_tiles;
+
+    const int H = ENV ? (p.fir_len - 1) / 2 : 0;
+    const int ring_len = C + 2 * H;
+    float *xwin = smem;                                            // mic_block x row
+    int *dref_lds = reinterpret_cast<int *>(xwin + p.mic_block * p.row);  // kMaxMicBlock
+    float *ring = reinterpret_cast<float *>(dref_lds + kMaxMicBlock) + wave * ring_len;
+
+    const int dir = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W + wave]);
+    const int dir0 = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W]);
+    const bool active = dir >= 0;
+    const double *vdir = p.dirs + 3 * (active ? dir : dir0);
+    const double *vref = p.dirs + 3 * dir0;
+
+    // Output blocks of a chunk start at tc - H (envelope) or tc (RF). seg_len is
+    // a multiple of 32 and the envelope start is pulled back by align_shift so
+    // that every block of 64 outputs begins on a 128-byte line.
+    const int g0 = seg * p.seg_len;
+    const int g1 = min(g0 + p.seg_len, p.T);
+    const int align_shift = ENV ? ((32 - (2 * H) % 32) % 32) : 0;
+    const int ystart = g0 - H - align_shift;
+    const int ylen = (g1 - g0) + 2 * H + align_shift;
+    const int nchunks = (ylen + C - 1) / C;
+    const int nblocks = (p.M + p.mic_block - 1) / p.mic_block;
+    const int two_halo = 2 * p.halo;
+
+    // Lane i of every wave holds the LDS offset (and fraction) of microphone
+    // i of the current block for this wave's direction.
+    int myoff = 0;
+    float myfrac = 0.0f;
+    auto block_geometry = [&](int blk) {
+        const int mic = blk * p.mic_block + lane;
+        if (lane < p.mic_block) {
+            int rel = 0;
+            if (mic < p.M) {
+                const double *r = p.mic + 3 * mic;
+                float f0, fw;
+                const int d0 = steer_whole<NEAR, LINEAR>(r, vref, p.fs, p.c, &f0);
+                const int dw = steer_whole<NEAR, LINEAR>(r, vdir, p.fs, p.c, &fw);
+                if (wave == 0) dref_lds[lane] = d0;
+                rel = min(max(dw - d0 + p.halo, 0), two_halo);  // the host bound keeps this in range
+                myfrac = fw;
+            } else if (wave == 0) {
+                dref_lds[lane] = 0;
+            }
+            myoff = lane * p.row + rel;
+        }
+    };
+
+    // Copy the taps' positions: the FIR reads them through the scalar cache.
+    const float *__restrict__ taps = p.taps;
+
+    if (nblocks == 1) block_geometry(0);
+    if constexpr (ENV) {
+        for (int i = lane; i < 2 * H; i += kWaveSize) ring[i] = 0.0f;
+    }
+
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int tc = ystart + ch * C;
+        Acc<N, CF, COMP> acc[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j].zero();
+
+        for (int blk = 0; blk < nblocks; ++blk) {
+            if (nblocks > 1) block_geometry(blk);
+            __syncthreads();  // reference delays visible; previous block's reads done
+            // ---- stage this block's channel windows into LDS ----
+            for (int i = wave; i < p.mic_block; i += W) {
+                const int mic = blk * p.mic_block + i;
+                float *dst = xwin + i * p.row;
+                if (mic < p.M) {
+                    const int base = tc + dref_lds[i] - p.halo;
+                    const size_t chan = (size_t)mic * (size_t)p.T;
+                    if (p.dtype == 0) {
+                        stage_row<0>(dst, p.x, chan, base, p.row, p.T, lane);
+                    } else if (p.dtype == 1) {
+                        stage_row<1>(dst, p.x, chan, base, p.row, p.T, lane);
+                    } else {
+                        stage_row<2>(dst, p.x, chan, base, p.row, p.T, lane);
+                    }
+                } else {
+                    for (int r = lane; r < p.row; r += kWaveSize) dst[r] = 0.0f;
+                }
+            }
+            __syncthreads();
+            // ---- hot loop: delayed samples -> roots -> power sums ----
+            if (active) {
+                const int nm = min(p.mic_block, p.M - blk * p.mic_block);
+#pragma unroll 2
+                for (int i = 0; i < nm; ++i) {
+                    const int off = __builtin_amdgcn_readlane(myoff, i);
+                    const float *src = xwin + off + lane;
+                    if constexpr (LINEAR) {
+                        const float fr = __builtin_bit_cast(
+                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myfrac), i));
+                        float v0[K], v1[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) {
+                            v0[j] = src[kWaveSize * j];
+                            v1[j] = src[kWaveSize * j + 1];
+                        }
+#pragma unroll
+                        for (int j = 0; j < K; ++j)
+                            accumulate<N, CF, COMP>(acc[j], __builtin_fmaf(fr, v1[j] - v0[j], v0[j]));
+                    } else {
+                        float v[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) v[j] = src[kWaveSize * j];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) accumulate<N, CF, COMP>(acc[j], v[j]);
+                    }
+                }
+            }
+        }
+
+        if (!active) continue;
+        // ---- epilogue: Newton-Girard, CF, store or envelope ----
+        const size_t orow = (size_t)dir * (size_t)p.T;
+        if constexpr (!ENV) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int t = tc + lane + kWaveSize * j;
+                const float y = finish_pixel<N, CF, COMP>(acc[j], p);
+                if (t < g1) __builtin_nontemporal_store(y, p.out + orow + t);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int t = tc + lane + kWaveSize * j;
+                const float y = finish_pixel<N, CF, COMP>(acc[j], p);
+                ring[2 * H + lane + kWaveSize * j] = (t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // env[t] for t = tc - H + o, o in [0, C): sum_k h[k] |y[t + H - k]|
+            float e[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) e[j] = 0.0f;
+            for (int k = 0; k < p.fir_len; ++k) {
+                const float h = taps[k];
+                const float *src = ring + 2 * H - k + lane;
+#pragma unroll
+                for (int j = 0; j < K; ++j) e[j] = __builtin_fmaf(h, src[kWaveSize * j], e[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int t = tc - H + lane + kWaveSize * j;
+                if (t >= g0 && t < g1) __builtin_nontemporal_store(e[j], p.out + orow + t);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // keep the last 2H values of |y| for the next chunk (2H <= C: no overlap)
+            for (int i = lane; i < 2 * H; i += kWaveSize) ring[i] = ring[C + i];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// Host-side launcher for one order: picks the instantiation for the flags.
+// Instantiated: every (CF, envelope, geometry) with nearest delays; linear
+// delays with CF; compensated sums for the far field with CF.
+template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
+hipError_t launch_one(const KernelParams &p, const LaunchShape &s, hipStream_t stream)
+{
+    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, COMP>;
+    static size_t lds_set = 64 * 1024;   // raised on demand; the limit only grows
+    if (s.lds_bytes > lds_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)s.lds_bytes);
+        if (e != hipSuccess) return e;
+        lds_set = s.lds_bytes;
+    }
+    hipLaunchKernelGGL(fn, dim3(s.grid), dim3(kDirsPerTile * kWaveSize), s.lds_bytes, stream, p);
+    return hipGetLastError();
+}
+
+// Resident workgroups per CU for this instantiation and LDS size.
+template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
+hipError_t occupancy_one(const LaunchShape &s, int *blocks)
+{
+    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, COMP>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(fn),
+                                                        kDirsPerTile * kWaveSize, s.lds_bytes);
+}
+
+template <int N>
+hipError_t launch_order(const KernelParams *p, const LaunchShape &s, hipStream_t stream, int *blocks)
+{
+#define DMAS_CASE(CF, ENV, NEAR, LIN, COMP)                                                  \
+    if (s.cf == CF && s.env == ENV && s.nearfield == NEAR && s.linear == LIN &&           \
+        s.compensated == COMP)                                                            \
+        return p ? launch_one<N, CF, ENV, NEAR, LIN, COMP>(*p, s, stream)                 \
+                 : occupancy_one<N, CF, ENV, NEAR, LIN, COMP>(s, blocks);
+    DMAS_CASE(false, false, false, false, false)
+    DMAS_CASE(false, true, false, false, false)
+    DMAS_CASE(true, false, false, false, false)
+    DMAS_CASE(true, true, false, false, false)
+    DMAS_CASE(false, false, true, false, false)
+    DMAS_CASE(false, true, true, false, false)
+    DMAS_CASE(true, false, true, false, false)
+    DMAS_CASE(true, true, true, false, false)
+    DMAS_CASE(true, false, false, true, false)
+    DMAS_CASE(true, true, false, true, false)
+    DMAS_CASE(true, false, true, true, false)
+    DMAS_CASE(true, true, true, true, false)
+    DMAS_CASE(true, false, false, false, true)
+    DMAS_CASE(true, true, false, false, true)
+#undef DMAS_CASE
+    return hipErrorNotSupported;
+}
+
+}  // namespace dmas

@@ -1,0 +1,12 @@
+// Kernel instantiations for DMAS order n = 3 (one order per unit so that the
+// orders compile in parallel).
+#include "dmas_kernel.hpp"
+
+namespace dmas {
+// With p != nullptr: launch. With p == nullptr: report resident workgroups
+// per CU for the shape in *blocks.
+hipError_t launch_order3(const KernelParams *p, const LaunchShape &s, hipStream_t stream, int *blocks)
+{
+    return launch_order<3>(p, s, stream, blocks);
+}
+}  // namespace dmas

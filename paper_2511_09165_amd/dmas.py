@@ -1,0 +1,232 @@
+"""ctypes binding of libdmas.so (the C ABI in include/dmas.h).
+
+Argument marshalling only: every step of the beamformer runs in the HIP
+kernels of libdmas.so. PyTorch supplies device memory and the current HIP
+stream. If the library is missing this module raises; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmas.so")
+
+DMAS_OK = 0
+STATUS_NAMES = {0: "DMAS_OK", 1: "DMAS_ERR_INVALID_ARG", 2: "DMAS_ERR_UNSUPPORTED",
+                3: "DMAS_ERR_OUT_OF_MEMORY", 4: "DMAS_ERR_DEVICE"}
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+EXPORTED = ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
+            "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass",
+            "dmas_last_error", "dmas_version")
+
+
+class DmasError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("num_mics", ctypes.c_int32), ("num_samples", ctypes.c_int32), ("num_dirs", ctypes.c_int32),
+        ("order", ctypes.c_int32), ("use_cf", ctypes.c_int32), ("geometry", ctypes.c_int32),
+        ("mic_pos", ctypes.POINTER(ctypes.c_double)), ("dirs", ctypes.POINTER(ctypes.c_double)),
+        ("fs", ctypes.c_double), ("c", ctypes.c_double), ("cf_eps", ctypes.c_double),
+        ("fir_taps", ctypes.POINTER(ctypes.c_float)), ("fir_len", ctypes.c_int32), ("fir_fc", ctypes.c_double),
+        ("in_dtype", ctypes.c_int32), ("ng_fp64", ctypes.c_int32), ("compensated", ctypes.c_int32),
+        ("delay_mode", ctypes.c_int32),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in (
+        "num_mics", "num_samples", "num_dirs", "order", "dirs_per_tile", "num_tiles", "samples_per_lane",
+        "chunk", "segment", "num_segments", "window_halo", "mics_per_block", "lds_bytes", "fir_len")]
+    _fields_ += [("workgroups", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libdmas.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(p)
+    st = ctypes.c_int
+    vp = ctypes.c_void_p
+    lib.dmas_plan_desc_init.argtypes = [ctypes.POINTER(PlanDesc)]
+    lib.dmas_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    lib.dmas_plan_destroy.argtypes = [vp]
+    lib.dmas_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.dmas_beamform.argtypes = [vp, vp, vp, ctypes.c_float, vp]
+    lib.dmas_envelope.argtypes = [vp, vp, vp, ctypes.c_float, vp]
+    lib.dmas_steering_delays.argtypes = [vp, vp, vp, vp]
+    lib.dmas_design_lowpass.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_float)]
+    for name in ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
+                 "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass"):
+        getattr(lib, name).restype = st
+    lib.dmas_last_error.restype = ctypes.c_char_p
+    lib.dmas_version.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != DMAS_OK:
+        msg = load_library().dmas_last_error().decode(errors="replace")
+        raise DmasError(status, msg)
+
+
+def version() -> str:
+    return load_library().dmas_version().decode()
+
+
+def design_lowpass(num_taps: int = 63, cutoff_hz: float = 5000.0, fs: float = 450e3) -> np.ndarray:
+    """The library's default envelope low-pass (host-side design)."""
+    out = np.zeros(num_taps, dtype=np.float32)
+    _check(load_library().dmas_design_lowpass(int(num_taps), float(cutoff_hz), float(fs),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Plan:
+    """A beamforming plan: geometry and taps resident on the current device.
+
+    Parameters follow ``dmas_plan_desc_t``. ``mic_pos`` is (M, 3) metres;
+    ``dirs`` is (D, 3) unit vectors (far field) or voxel centres (near field).
+    """
+
+    def __init__(self, mic_pos, dirs, num_samples: int, order: int, fs: float, c: float = 343.0,
+                 use_cf: bool = True, nearfield: bool = False, fir_taps=None, fir_len: int = 63,
+                 fir_fc: float = 5000.0, in_dtype: str = "f32", ng_fp64: bool = False,
+                 compensated: bool = False, linear: bool = False, cf_eps: float = 1e-20):
+        lib = load_library()
+        self._lib = lib
+        self._handle = ctypes.c_void_p()
+        mic = np.ascontiguousarray(np.asarray(mic_pos, dtype=np.float64))
+        dv = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64))
+        if mic.ndim != 2 or mic.shape[1] != 3 or dv.ndim != 2 or dv.shape[1] != 3:
+            raise ValueError("mic_pos and dirs must be (N, 3)")
+        if in_dtype not in DTYPES:
+            raise ValueError(f"in_dtype must be one of {sorted(DTYPES)}")
+        d = PlanDesc()
+        _check(lib.dmas_plan_desc_init(ctypes.byref(d)))
+        d.num_mics, d.num_samples, d.num_dirs = mic.shape[0], int(num_samples), dv.shape[0]
+        d.order, d.use_cf, d.geometry = int(order), int(bool(use_cf)), int(bool(nearfield))
+        d.mic_pos = mic.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.dirs = dv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.fs, d.c, d.cf_eps = float(fs), float(c), float(cf_eps)
+        taps = None
+        if fir_taps is not None:
+            taps = np.ascontiguousarray(np.asarray(fir_taps, dtype=np.float32))
+            d.fir_taps = taps.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            d.fir_len = taps.size
+        else:
+            d.fir_len = int(fir_len)
+        d.fir_fc = float(fir_fc)
+        d.in_dtype = DTYPES[in_dtype]
+        d.ng_fp64, d.compensated, d.delay_mode = int(bool(ng_fp64)), int(bool(compensated)), int(bool(linear))
+        _check(lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(self._handle)))
+        self.num_mics, self.num_samples, self.num_dirs = d.num_mics, d.num_samples, d.num_dirs
+        self.order, self.in_dtype = int(order), in_dtype
+        self.use_cf, self.nearfield, self.linear = bool(use_cf), bool(nearfield), bool(linear)
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            self._lib.dmas_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return int(self._handle.value or 0)
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(self._lib.dmas_plan_query(self._handle, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in PlanInfo._fields_}
+
+    # -- launches -----------------------------------------------------------
+    def _check_input(self, x):
+        import torch
+        want = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.in_dtype]
+        if not x.is_cuda or x.dtype != want or tuple(x.shape) != (self.num_mics, self.num_samples) \
+                or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous {want} device tensor of shape "
+                             f"({self.num_mics}, {self.num_samples}); got {x.dtype} {tuple(x.shape)}")
+
+    def _out(self, x, out):
+        import torch
+        if out is None:
+            return torch.empty((self.num_dirs, self.num_samples), dtype=torch.float32, device=x.device)
+        if out.dtype != torch.float32 or tuple(out.shape) != (self.num_dirs, self.num_samples) \
+                or not out.is_contiguous() or out.device != x.device:
+            raise ValueError("out must be a contiguous float32 (D, T) tensor on the input's device")
+        return out
+
+    def beamform(self, x, out=None, in_scale: float = 1.0, stream=None):
+        """DMAS-n (+CF) image, (D, T) float32."""
+        self._check_input(x)
+        out = self._out(x, out)
+        _check(self._lib.dmas_beamform(self._handle, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), float(in_scale),
+                                       ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def envelope(self, x, out=None, in_scale: float = 1.0, stream=None):
+        """DMAS-n (+CF) image followed by the envelope filter, (D, T) float32."""
+        self._check_input(x)
+        out = self._out(x, out)
+        _check(self._lib.dmas_envelope(self._handle, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), float(in_scale),
+                                       ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def steering_delays(self, stream=None):
+        """(whole, frac) device tensors of shape (D, M): the delays the kernels use."""
+        import torch
+        whole = torch.empty((self.num_dirs, self.num_mics), dtype=torch.int32, device="cuda")
+        frac = torch.empty((self.num_dirs, self.num_mics), dtype=torch.float32, device="cuda")
+        _check(self._lib.dmas_steering_delays(self._handle, ctypes.c_void_p(whole.data_ptr()),
+                                              ctypes.c_void_p(frac.data_ptr()),
+                                              ctypes.c_void_p(_stream_handle(stream))))
+        return whole, frac
+
+
+def plan_for_frame(frame, **kw) -> Plan:
+    """Plan for a ``synth.Frame``-like object (mic_pos, dirs, fs, c, order, use_cf, nearfield)."""
+    args = dict(mic_pos=frame.mic_pos, dirs=frame.dirs, num_samples=frame.num_samples, order=frame.order,
+                fs=frame.fs, c=frame.c, use_cf=frame.use_cf, nearfield=frame.nearfield)
+    args.update(kw)
+    return Plan(**args)

@@ -1,0 +1,278 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (see tests/_parity.py): T1 peak-normalised <= 1e-4, T2 per-pixel
+rounding bound from the oracle's conditioning diagnostics, T3 envelope dB
+deviation. Integer work (steering delays) is compared bit for bit.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _parity import check_t1, check_t2, check_t3, env_bound, root_rel_error, y_bound
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _plan(frame, **kw):
+    from paper_2511_09165_amd import plan_for_frame
+    return plan_for_frame(frame, **kw)
+
+
+def _run(frame, x32, env=False, taps=None, rows=None, **kw):
+    """GPU image (float64 copy), restricted to ``rows`` if given."""
+    with _plan(frame, fir_taps=taps, **kw) as plan:
+        x = torch.from_numpy(np.ascontiguousarray(x32)).cuda()
+        out = plan.envelope(x) if env else plan.beamform(x)
+        torch.cuda.synchronize()
+        out = out if rows is None else out[torch.as_tensor(rows, device="cuda")]
+        return out.cpu().numpy().astype(np.float64)
+
+
+def _compare(frame, x32, rows=None, check_env=True, taps=None, t2=True, interp=False, **kw):
+    n, M = frame.order, frame.num_mics
+    x64 = x32.astype(np.float64) if x32.dtype != np.float64 else x32
+    y_ref, dg = oracle.frame_rows(frame, x=x64, rows=rows, diag=True, interp=interp)
+    y = _run(frame, x32, rows=rows, linear=interp, **kw)
+    e1 = check_t1(y, y_ref)
+    worst = None
+    if t2:
+        tol = y_bound(dg, M, n, frame.use_cf, root_rel_error(x64))
+        worst = check_t2(y, y_ref, tol)
+    res = dict(t1=e1, t2=worst)
+    if check_env:
+        taps = oracle.lowpass_taps(63, 5000.0, frame.fs) if taps is None else taps
+        taps32 = np.asarray(taps, dtype=np.float32)
+        env_ref = oracle.envelope(y_ref, taps32.astype(np.float64))
+        env = _run(frame, x32, env=True, taps=taps32, rows=rows, linear=interp, **kw)
+        res["env_t1"] = check_t1(env, env_ref)
+        if t2:
+            res["env_t2"] = check_t2(env, env_ref, env_bound(tol, np.abs(y_ref), taps32, oracle.envelope))
+        res["env_db"] = check_t3(env, env_ref, tol_db=0.05)
+    return res
+
+
+# ---------------------------------------------------------------------------
+# Steering delays: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["config2_far", "config5_near", "random_far_linear", "random_near_linear"])
+def test_steering_delays_bit_exact(case):
+    _say(f"delays {case}")
+    if case == "config2_far":
+        f = synth.config2()
+        linear = False
+    elif case == "config5_near":
+        f = synth.config5(voxels=(32, 32, 8))
+        linear = False
+    else:
+        f = synth.random_frame(np.random.default_rng(3), 37, 300, 64, 3, nearfield=case.endswith("near_linear"))
+        linear = True
+    with _plan(f, linear=linear) as plan:
+        whole, frac = plan.steering_delays()
+        torch.cuda.synchronize()
+        whole, frac = whole.cpu().numpy(), frac.cpu().numpy()
+    if linear:
+        w_ref, f_ref = oracle.delays_frac(f.mic_pos, f.dirs, f.fs, f.c, f.nearfield)
+        assert np.array_equal(whole, w_ref.astype(np.int32))
+        assert np.array_equal(frac, f_ref.astype(np.float32))
+    else:
+        d_ref = oracle.delays(f.mic_pos, f.dirs, f.fs, f.c, f.nearfield)
+        assert np.array_equal(whole, d_ref.astype(np.int32))
+        assert np.all(frac == 0)
+
+
+# ---------------------------------------------------------------------------
+# Whole images at small sizes (several tiles, ragged tails)
+# ---------------------------------------------------------------------------
+
+def test_config1_parity():
+    """Order-2 DMAS+CF, 8 mics, 64 azimuths, 1024 samples: every pixel, RF and envelope."""
+    f = synth.config1()
+    _say("config1 n=2 cf")
+    res = _compare(f, f.x_f32())
+    _say(f"config1 {res}")
+
+
+@pytest.mark.parametrize("nearfield", [False, True])
+@pytest.mark.parametrize("use_cf", [False, True])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_orders(n, use_cf, nearfield):
+    rng = np.random.default_rng(100 * n + 10 * use_cf + nearfield)
+    f = synth.random_frame(rng, 12, 21, 777, n, nearfield=nearfield, use_cf=use_cf)
+    _say(f"orders n={n} cf={use_cf} near={nearfield}")
+    _compare(f, f.x_f32())
+
+
+@pytest.mark.parametrize("nearfield", [False, True])
+def test_microphone_blocks(nearfield):
+    """M = 150 spans three LDS microphone blocks (64 + 64 + 22)."""
+    f = synth.random_frame(np.random.default_rng(7), 150, 13, 600, 3, nearfield=nearfield)
+    _say(f"mic blocks near={nearfield}")
+    _compare(f, f.x_f32())
+
+
+@pytest.mark.parametrize("M,D,T,n", [(1, 1, 1, 1), (3, 1, 2, 3), (5, 9, 63, 2), (8, 8, 255, 5), (8, 8, 256, 5),
+                                     (8, 8, 257, 5), (9, 17, 513, 4), (6, 3, 1000, 6)])
+def test_edge_sizes(M, D, T, n):
+    f = synth.random_frame(np.random.default_rng(M * 1000 + D * 10 + T), M, D, T, n)
+    _say(f"edge M={M} D={D} T={T} n={n}")
+    _compare(f, f.x_f32())
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_tiny_records_at_broadside(T):
+    """Records of 1-3 samples with every delay zero (microphones on the z axis, broadside direction)."""
+    rng = np.random.default_rng(T)
+    M = 4
+    mic = np.zeros((M, 3))
+    f = synth.Frame("tiny", rng.standard_normal((M, T)), mic, np.array([[0.0, 0.0, 1.0]] * 3), 450e3, 343.0,
+                    3, True, False)
+    res = _compare(f, f.x_f32())
+
+
+def test_zero_and_constant_channels():
+    """All-zero input gives 0 (CF guard); identical channels at broadside give C(M,n)|x|."""
+    M, T = 16, 300
+    mic = synth.disc_array(np.random.default_rng(1), M, 0.1)
+    dirs = np.array([[0.0, 0.0, 1.0], [0.3, 0.0, np.sqrt(1 - 0.09)]])
+    f = synth.Frame("zeros", np.zeros((M, T)), mic, dirs, 450e3, 343.0, 5, True, False)
+    assert np.all(_run(f, f.x_f32()) == 0.0)
+    assert np.all(_run(f, f.x_f32(), env=True) == 0.0)
+    row = np.random.default_rng(2).standard_normal(T)
+    f.x = np.tile(row, (M, 1))
+    y = _run(f, f.x_f32())
+    want = math.comb(16, 5) * row.astype(np.float32).astype(np.float64)  # C(M,n) sgn(x)^5 |x|
+    np.testing.assert_allclose(y[0], want, rtol=2e-5)
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads in the benchmark's launch configuration, sampled rows
+# ---------------------------------------------------------------------------
+
+def _sample_rows(f, k, seed):
+    rng = np.random.default_rng(seed)
+    rows = set(rng.choice(f.num_dirs, size=k, replace=False).tolist())
+    rows.update([0, f.num_dirs - 1])
+    return sorted(rows)
+
+
+def test_config2_full_size_sampled_rows():
+    """eRTIS-like frame: M=32, D=4186, T=16384, order 5 + CF; full launch, oracle on sampled rows."""
+    f = synth.config2()
+    rows = _sample_rows(f, 22, 5)
+    # also the direction with the strongest DAS response (a bright pixel)
+    das = oracle.dmas_rows(f.x, f.mic_pos, f.dirs, f.fs, f.c, 1, use_cf=False, rows=rows)
+    _say(f"config2 full size, rows {rows[:4]}...")
+    res = _compare(f, f.x_f32(), rows=rows)
+    _say(f"config2 {res} (das peak {np.abs(das).max():.3g})")
+
+
+def test_config5_full_size_sampled_rows():
+    """Near field: M=1024 (16 LDS blocks), 64x64x32 voxels, T=2048, order 3 + CF; oracle on sampled rows."""
+    f = synth.config5()
+    rows = _sample_rows(f, 10, 6)
+    _say(f"config5 full size, rows {rows[:4]}...")
+    res = _compare(f, f.x_f32(), rows=rows, taps=oracle.lowpass_taps(63, 5000.0, f.fs))
+    _say(f"config5 {res}")
+
+
+# ---------------------------------------------------------------------------
+# Invariants (bitwise)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_sign_flip_bitwise(n):
+    """S(-x) = (-1)^n S(x) bit for bit (every term has degree n; the envelope sees |y|)."""
+    f = synth.random_frame(np.random.default_rng(50 + n), 16, 24, 900, n)
+    x = f.x_f32()
+    y = _run(f, x)
+    yn = _run(f, -x)
+    assert np.array_equal(yn, (-1) ** n * y)
+    assert np.array_equal(_run(f, x, env=True), _run(f, -x, env=True))
+
+
+def test_power_of_two_scale_bitwise():
+    """in_scale multiplies the result; a power of two is exact."""
+    f = synth.random_frame(np.random.default_rng(60), 10, 16, 500, 3)
+    x = torch.from_numpy(f.x_f32()).cuda()
+    with _plan(f) as plan:
+        a = plan.beamform(x).cpu().numpy()
+        b = plan.beamform(x, in_scale=4.0).cpu().numpy()
+    assert np.array_equal(b, 4.0 * a)
+
+
+def test_determinism_and_streams():
+    """Same bits on repeated runs and on two concurrent streams sharing one plan."""
+    f = synth.random_frame(np.random.default_rng(61), 24, 40, 2000, 5)
+    x = torch.from_numpy(f.x_f32()).cuda()
+    with _plan(f) as plan:
+        ref = plan.envelope(x).cpu().numpy()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            a = plan.envelope(x, stream=s1)
+        with torch.cuda.stream(s2):
+            b = plan.envelope(x, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), ref) and np.array_equal(b.cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------------------
+# Precision forms and linear delays
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_half_precision_storage(dtype):
+    """FP16/BF16 channels with a per-frame scale: parity against the oracle on the dequantised values."""
+    f = synth.config3(order=5)
+    tdt = torch.float16 if dtype == "f16" else torch.bfloat16
+    amax = np.abs(f.x).max()
+    scale = 2.0 ** np.floor(np.log2(amax / 16384.0)) if dtype == "f16" else 1.0
+    xq = torch.from_numpy(f.x / scale).to(tdt)
+    x_deq = xq.float().numpy().astype(np.float64) * scale
+    rows = list(range(f.num_dirs))
+    y_ref, dg = oracle.frame_rows(f, x=x_deq, diag=True)
+    with _plan(f, in_dtype=dtype) as plan:
+        y = plan.beamform(xq.cuda(), in_scale=scale).cpu().numpy().astype(np.float64)
+    check_t1(y, y_ref)
+    check_t2(y, y_ref, y_bound(dg, f.num_mics, 5, True, root_rel_error(x_deq)))
+    assert rows
+
+
+@pytest.mark.parametrize("variant", [dict(ng_fp64=True), dict(compensated=True),
+                                     dict(ng_fp64=True, compensated=True)])
+@pytest.mark.parametrize("n", [2, 5, 7])
+def test_precision_variants(n, variant):
+    f = synth.config3(order=n)
+    _say(f"precision n={n} {variant}")
+    _compare(f, f.x_f32(), **variant)
+
+
+@pytest.mark.parametrize("nearfield", [False, True])
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_linear_delays(n, nearfield):
+    """Linear fractional delays (interpolation between the two neighbouring samples)."""
+    f = synth.random_frame(np.random.default_rng(70 + n), 14, 19, 640, n, nearfield=nearfield)
+    _say(f"linear n={n} near={nearfield}")
+    _compare(f, f.x_f32(), interp=True, t2=False)
+
+
+def test_bad_inputs_rejected():
+    from paper_2511_09165_amd import DmasError
+    f = synth.random_frame(np.random.default_rng(80), 4, 3, 50, 2)
+    with _plan(f) as plan:
+        with pytest.raises(ValueError):
+            plan.beamform(torch.zeros((4, 50), dtype=torch.float64, device="cuda"))
+        with pytest.raises(ValueError):
+            plan.beamform(torch.zeros((4, 49), dtype=torch.float32, device="cuda"))
+        with pytest.raises(DmasError):
+            plan.beamform(torch.zeros((4, 50), dtype=torch.float32, device="cuda"), in_scale=0.0)
