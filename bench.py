@@ -68,7 +68,7 @@ def pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_09165_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("dmas_api.hip", "dmas_internal.hpp", "dmas_kernel.hpp", "dmas_order5.hip"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -86,14 +86,15 @@ def measured_traffic(workload_key: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(frame, taps, stride: int = 4):
+def cpu_baseline(frame, fir_len: int, stride: int = 4) -> dict:
     """Time the FP64 oracle on every ``stride``-th direction of the same frame (rows + envelope)."""
     import oracle
+    taps = oracle.lowpass_taps(fir_len, 5000.0, frame.fs)
     rows = list(range(0, frame.num_dirs, stride))
     x64 = frame.x_f32().astype(np.float64)
     t0 = time.perf_counter()
     y = oracle.frame_rows(frame, x=x64, rows=rows)
-    oracle.envelope(y, taps.astype(np.float64))
+    oracle.envelope(y, taps)
     dt = time.perf_counter() - t0
     pix = len(rows) * frame.num_samples
     return {"value": pix / dt, "unit": "direction*samples/s", "cores": oracle.num_threads(), "kind": "oracle",
@@ -101,11 +102,147 @@ def cpu_baseline(frame, taps, stride: int = 4):
                       f"samples, order-5 DMAS+CF+envelope, FP64, {dt:.2f} s wall"}
 
 
+def _timed(launch, steps: int, warmup: int, stream):
+    """(wall ms per step, kernel ms per launch from HIP events on the launch stream)."""
+    import torch
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        launch()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall * 1e3 / steps, ev0.elapsed_time(ev1) / steps
+
+
+def _roofline(slots_per_pixel: int, pixels: int, kernel_ms: float, traffic=None) -> dict:
+    achieved = slots_per_pixel * pixels / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12, "unit": "TOP/s",
+            "frac": achieved / VALU_SLOTS_PER_S, "traffic": traffic, "kernel_ms": kernel_ms,
+            "ops_per_pixel": slots_per_pixel, "op": "VALU lane-instruction issue slot (transcendental = 2)"}
+
+
+def _base_record(args, value, ms_per_step, dtype, config) -> dict:
+    return {"metric": "direction*samples/sec, order-5 DMAS+CF, 32 mics", "value": value,
+            "unit": "direction*samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic (seeded)", "config": config}
+
+
+def bench_headline(args) -> dict:
+    """Order-5 DMAS + CF + envelope on the eRTIS-like frame (the headline line)."""
+    import torch
+
+    import synth
+    from paper_2511_09165_amd import plan_for_frame
+
+    frame = synth.config2()
+    M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
+    fir_len = 63
+    plan = plan_for_frame(frame, fir_len=fir_len)
+    x = torch.from_numpy(frame.x_f32()).cuda()
+    out = torch.empty((D, T), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), args.steps, args.warmup, stream)
+    pixels = D * T
+    workload_key = f"config2 M={M} D={D} T={T} n={n} cf=1 env L={fir_len}"
+    rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
+        "workload": "eRTIS-like frame: order-5 DMAS+CF+envelope, M=32 mics (12 cm sparse disc), "
+                    "91x46 az/el directions, T=16384 samples at 450 kHz, 63-tap envelope FIR",
+        "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len})
+    rec["data"] = "synthetic (seeded eRTIS-like pulse-echo frame)"
+    rec["roofline"] = _roofline(pixel_slots(M, n, True, fir_len), pixels, kernel_ms, measured_traffic(workload_key))
+    if args.extra:
+        reps = max(5, args.steps // 2)
+        extra = {"rf_ms": _timed(lambda: plan.beamform(x, out=out), reps, 2, stream)[1]}
+        with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
+            extra["no_cf_env_ms"] = _timed(lambda: p2.envelope(x, out=out), reps, 2, stream)[1]
+        with plan_for_frame(frame, fir_len=fir_len, ng_fp64=True) as p3:
+            extra["ng_fp64_env_ms"] = _timed(lambda: p3.envelope(x, out=out), reps, 2, stream)[1]
+        extra["plan"] = plan.info()
+        rec["extra"] = extra
+    rec["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(frame, fir_len)
+    plan.close()
+    return rec
+
+
+def bench_nearfield(args) -> dict:
+    """Near-field order-3 DMAS + CF + envelope: 1024 microphones, 64 x 64 x 32 voxels, 2048 samples."""
+    import torch
+
+    import synth
+    from paper_2511_09165_amd import plan_for_frame
+
+    frame = synth.config5()
+    M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
+    fir_len = 63
+    with plan_for_frame(frame, fir_len=fir_len) as plan:
+        x = torch.from_numpy(frame.x_f32()).cuda()
+        out = torch.empty((D, T), dtype=torch.float32, device="cuda")
+        steps = max(3, args.steps // 10)
+        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, 2,
+                                        torch.cuda.current_stream())
+        info = plan.info()
+    pixels = D * T
+    rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
+        "workload": "near-field passive imaging: order-3 DMAS+CF+envelope, 32x32 grid M=1024, "
+                    "64x64x32 voxels, T=2048 at 192 kHz", "M": M, "D": D, "T": T, "order": n, "cf": True,
+        "fir_len": fir_len})
+    rec["metric"] = "direction*samples/sec, order-3 DMAS+CF, 1024 mics, near field"
+    rec["steps"] = steps
+    rec["roofline"] = _roofline(pixel_slots(M, n, True, fir_len), pixels, kernel_ms)
+    rec["extra"] = {"plan": info}
+    return rec
+
+
+def bench_precision(args) -> list:
+    """Throughput of the precision forms at the eRTIS-like frame's shape, orders 2..7."""
+    import torch
+
+    import synth
+    from paper_2511_09165_amd import plan_for_frame
+
+    base = synth.config2()
+    D, T, M = base.num_dirs, base.num_samples, base.num_mics
+    x32 = base.x_f32()
+    amax = float(np.abs(x32).max())
+    f16_scale = 2.0 ** np.floor(np.log2(amax / 16384.0))
+    inputs = {"f32": (torch.from_numpy(x32).cuda(), 1.0),
+              "f16": (torch.from_numpy(x32 / f16_scale).to(torch.float16).cuda(), f16_scale),
+              "bf16": (torch.from_numpy(x32).to(torch.bfloat16).cuda(), 1.0)}
+    out = torch.empty((D, T), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    recs = []
+    steps = max(5, args.steps // 5)
+    for n in (2, 3, 4, 5, 6, 7):
+        base.order = n
+        for dt in ("f32", "f16", "bf16"):
+            for ng64 in (False, True):
+                for comp in (False, True):
+                    xin, sc = inputs[dt]
+                    with plan_for_frame(base, in_dtype=dt, ng_fp64=ng64, compensated=comp) as plan:
+                        _, kms = _timed(lambda: plan.envelope(xin, out=out, in_scale=sc), steps, 2, stream)
+                    recs.append({"order": n, "storage": dt, "ng_fp64": ng64, "kahan": comp, "kernel_ms": kms,
+                                 "value": D * T / (kms * 1e-3)})
+    for r in recs:
+        plain = next(q for q in recs if q["order"] == r["order"] and q["storage"] == "f32" and not q["ng_fp64"]
+                     and not q["kahan"])
+        r["speedup_vs_plain_f32"] = plain["kernel_ms"] / r["kernel_ms"]
+    return recs
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="erti32", choices=["erti32", "nearfield", "precision"],
+                    help="erti32: the headline frame (default); nearfield: 1024-mic voxel imaging; "
+                         "precision: FP16/BF16 storage, FP64 Newton-Girard and Kahan sums, orders 2-7")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also time RF output, CF off and FP64 Newton-Girard")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -118,8 +255,7 @@ def main(argv=None) -> int:
 
     import torch
 
-    import synth
-    from paper_2511_09165_amd import load_library, plan_for_frame
+    from paper_2511_09165_amd import load_library
 
     load_library()
     if not torch.cuda.is_available():
@@ -134,90 +270,13 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": args.steps}), flush=True)
         return 0
-    frame = synth.config2()
-    M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
-    fir_len = 63
-    plan = plan_for_frame(frame, fir_len=fir_len)
-    taps = None
-    try:
-        import oracle
-        taps = oracle.lowpass_taps(fir_len, 5000.0, frame.fs)
-    except Exception:
-        taps = None
-    x = torch.from_numpy(frame.x_f32()).cuda()
-    out = torch.empty((D, T), dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        plan.envelope(x, out=out)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.envelope(x, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = ev0.elapsed_time(ev1) / args.steps
-    ms_per_step = wall * 1e3 / args.steps
-    pixels = D * T
-    value = pixels / (ms_per_step * 1e-3)
-
-    slots = pixel_slots(M, n, True, fir_len) * pixels
-    achieved = slots / (kernel_ms * 1e-3)
-    workload_key = f"config2 M={M} D={D} T={T} n={n} cf=1 env L={fir_len}"
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12,
-                "unit": "TOP/s", "frac": achieved / VALU_SLOTS_PER_S, "traffic": measured_traffic(workload_key),
-                "kernel_ms": kernel_ms, "ops_per_pixel": pixel_slots(M, n, True, fir_len),
-                "op": "VALU lane-instruction issue slot (transcendental = 2)"}
-
-    extra = {}
-    if args.extra:
-        def timeit(fn, reps=max(5, args.steps // 2)):
-            fn()
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                fn()
-            b.record(stream)
-            torch.cuda.synchronize()
-            return a.elapsed_time(b) / reps
-        extra["rf_ms"] = timeit(lambda: plan.beamform(x, out=out))
-        with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
-            extra["no_cf_env_ms"] = timeit(lambda: p2.envelope(x, out=out))
-        with plan_for_frame(frame, fir_len=fir_len, ng_fp64=True) as p3:
-            extra["ng_fp64_env_ms"] = timeit(lambda: p3.envelope(x, out=out))
-        extra["plan"] = plan.info()
-
-    cpu = None
-    if not args.no_cpu_baseline and taps is not None:
-        cpu = cpu_baseline(frame, taps)
-
-    rec = {
-        "metric": "direction*samples/sec, order-5 DMAS+CF, 32 mics",
-        "value": value,
-        "unit": "direction*samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded eRTIS-like pulse-echo frame)",
-        "config": {"workload": "eRTIS-like frame: order-5 DMAS+CF+envelope, M=32 mics (12 cm sparse disc), "
-                               "91x46 az/el directions, T=16384 samples at 450 kHz, 63-tap envelope FIR",
-                   "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    if extra:
-        rec["extra"] = extra
-    plan.close()
-    print(json.dumps(rec), flush=True)
+    if args.workload == "erti32":
+        print(json.dumps(bench_headline(args)), flush=True)
+    elif args.workload == "nearfield":
+        print(json.dumps(bench_nearfield(args)), flush=True)
+    else:
+        for r in bench_precision(args):
+            print(json.dumps(r), flush=True)
     return 0
 
 
