@@ -235,12 +235,80 @@ def bench_precision(args) -> list:
     return recs
 
 
+def bench_serving(args) -> list:
+    """Serving: Poisson arrivals of heterogeneous pulse-echo frames, batched server vs one launch per frame.
+
+    Frames: arrays of 16/32/64 microphones (6-20 cm discs), az/el grids of
+    1024-8192 directions, orders 3 and 5, 4096-16384 samples, FP32, envelope
+    output kept on the device (released at completion). Each rate point
+    offers ``rate * duration`` frames; latency = completion - scheduled arrival.
+    """
+    import synth
+    from paper_2511_09165_amd import DmasError, Server, plan_for_frame, server_clock
+
+    pool = synth.serving_pool(n_arrays_per_m=4, max_frames=args.serving_pool)
+    plans = [plan_for_frame(f) for f in pool]
+    xs = [f.x_f32() for f in pool]
+    pix = [f.num_dirs * f.num_samples for f in pool]
+    rng = np.random.default_rng(2511091654)
+    rates = [float(r) for r in args.serving_rates.split(",")]
+    out = []
+    modes = [("batched", dict(num_streams=2, max_batch=64)), ("one_launch_per_frame", dict(num_streams=1, max_batch=1))]
+    for rate in rates:
+        n_frames = max(20, int(rate * args.serving_duration))
+        gaps = rng.exponential(1.0 / rate, size=n_frames)
+        picks = rng.integers(0, len(pool), size=n_frames)
+        for mode, kw in modes:
+            with Server(hbm_budget=64 << 30, staging=2 << 30, **kw) as srv:
+                # warm up every plan once (first launches of each kernel)
+                for k in range(len(pool)):
+                    srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
+                srv.drain(600)
+                srv.completed(100000)
+                launches0 = srv.stats()["launches"]
+                t0 = server_clock() + 0.05
+                arrivals = t0 + np.cumsum(gaps)
+                busy_retries = 0
+                for a, k in zip(arrivals, picks):
+                    while server_clock() < a:
+                        pass
+                    while True:
+                        try:
+                            srv.submit(plans[k], xs[k], envelope=True, auto_release=True, arrival=float(a))
+                            break
+                        except DmasError as e:
+                            if e.status != 5:
+                                raise
+                            busy_retries += 1
+                srv.drain(600)
+                recs = srv.completed(n_frames + 10)
+                st = srv.stats()
+            lat = np.array([r["t_done"] - r["t_arrival"] for r in recs]) * 1e3
+            done = np.array([r["t_done"] for r in recs])
+            total_pix = float(sum(pix[k] for k in picks))
+            span = float(done.max() - arrivals[0])
+            out.append({"workload": "serving", "mode": mode, "offered_frames_per_s": rate, "frames": len(recs),
+                        "achieved_frames_per_s": len(recs) / span,
+                        "direction_samples_per_s": total_pix / span,
+                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "max_ms": float(lat.max()), "launches": st["launches"] - launches0,
+                        "mean_frames_per_launch": len(recs) / max(1, st["launches"] - launches0),
+                        "hbm_peak_gb": st["hbm_peak"] / 1e9, "busy_retries": busy_retries})
+            print(json.dumps(out[-1]), flush=True)
+    for p in plans:
+        p.close()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="erti32", choices=["erti32", "nearfield", "precision"],
+    ap.add_argument("--serving-rates", default="250,500,1000,1500,2000", help="offered frames/s (serving)")
+    ap.add_argument("--serving-duration", type=float, default=2.0, help="seconds of arrivals per rate (serving)")
+    ap.add_argument("--serving-pool", type=int, default=48, help="distinct frames in the serving pool")
+    ap.add_argument("--workload", default="erti32", choices=["erti32", "nearfield", "precision", "serving"],
                     help="erti32: the headline frame (default); nearfield: 1024-mic voxel imaging; "
                          "precision: FP16/BF16 storage, FP64 Newton-Girard and Kahan sums, orders 2-7")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -274,6 +342,8 @@ def main(argv=None) -> int:
         print(json.dumps(bench_headline(args)), flush=True)
     elif args.workload == "nearfield":
         print(json.dumps(bench_nearfield(args)), flush=True)
+    elif args.workload == "serving":
+        bench_serving(args)
     else:
         for r in bench_precision(args):
             print(json.dumps(r), flush=True)

@@ -68,7 +68,9 @@ typedef enum {
     DMAS_ERR_INVALID_ARG = 1,   /* bad pointer, size, order or flag */
     DMAS_ERR_UNSUPPORTED = 2,   /* valid request this build does not serve */
     DMAS_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
-    DMAS_ERR_DEVICE = 4         /* a HIP call or kernel launch failed */
+    DMAS_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
+    DMAS_ERR_BUSY = 5,          /* serving: staging memory full, submit again later */
+    DMAS_ERR_TIMEOUT = 6        /* serving: a wait ended before the frame was done */
 } dmas_status_t;
 
 typedef enum { DMAS_FARFIELD = 0, DMAS_NEARFIELD = 1 } dmas_geometry_t;
@@ -154,6 +156,98 @@ dmas_status_t dmas_steering_delays(dmas_plan_t plan, int32_t *d_whole, float *d_
 /* Default envelope low-pass design (host only): Hamming-windowed sinc of
  * odd length L and cut-off fc at sample rate fs, unit DC gain. */
 dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *taps);
+
+/* ------------------------------------------------------------------------
+ * Serving runtime: continuous batching of heterogeneous frames.
+ *
+ * Not part of the paper's method (which images one frame at a time); it is
+ * the request loop that keeps the GPU busy when frames of different arrays,
+ * direction grids, orders and lengths arrive while others are running:
+ *   - submit copies the frame's input into pinned staging memory and queues it;
+ *   - a scheduler thread admits queued frames in arrival order while their
+ *     device input and output fit in the HBM budget (an arena allocated once),
+ *     copies the input on a copy stream, and groups admitted frames into one
+ *     multi-frame launch (frames with the same CF / envelope / geometry flags,
+ *     nearest delays, plain sums; others are launched one by one) on the next
+ *     free compute stream, so a new batch starts while earlier ones finish;
+ *   - completion is observed from stream events and stamped per frame.
+ * Each frame's pixels are computed by the same device code as
+ * dmas_beamform / dmas_envelope, so a frame gives the same bits alone and
+ * in a batch. Plans stay owned by the caller and must outlive their frames.
+ * All times are seconds on dmas_server_clock().
+ * ------------------------------------------------------------------------ */
+typedef struct dmas_server_s *dmas_server_t;
+
+typedef struct {
+    int64_t hbm_budget_bytes;  /* device memory for admitted frames' inputs + outputs (> 0) */
+    int64_t staging_bytes;     /* pinned host memory for queued inputs; 0 selects 256 MiB */
+    int32_t num_streams;       /* launches in flight at once; 0 selects 2 */
+    int32_t max_batch_frames;  /* frames per launch; 0 selects 64; 1 = one plain launch per frame */
+} dmas_server_desc_t;
+
+/* submit flags */
+#define DMAS_SUBMIT_ENVELOPE 1     /* envelope image (else the RF image) */
+#define DMAS_SUBMIT_AUTO_RELEASE 2 /* free the frame's device memory at completion; the
+                                      frame's record is kept for dmas_server_completed */
+
+typedef struct {
+    uint64_t ticket;
+    int32_t state;         /* 0 queued, 1 admitted, 2 launched, 3 done, -1 failed */
+    int32_t batch_frames;  /* frames in the launch that carried this frame */
+    double t_arrival;      /* caller-given arrival time (or submit time) */
+    double t_admit;        /* device memory granted, input copy issued */
+    double t_launch;       /* launch issued */
+    double t_done;         /* completion observed */
+    float *d_out;          /* device result, D x T FP32; NULL once released */
+    int64_t pixels;        /* D * T */
+} dmas_frame_info_t;
+
+typedef struct {
+    int64_t submitted, completed, failed, launches, batched_frames;
+    int64_t queued, admitted_not_launched, in_flight;
+    int64_t hbm_in_use, hbm_peak, hbm_budget;
+} dmas_server_stats_t;
+
+/* Seconds on the serving clock (monotonic). */
+double dmas_server_clock(void);
+
+/* Create a server on the current device: allocates the HBM arena
+ * (hbm_budget_bytes) and pinned staging, creates the streams and starts the
+ * scheduler thread. */
+dmas_status_t dmas_server_create(const dmas_server_desc_t *desc, dmas_server_t *out);
+
+/* Queue one frame. h_x: host memory, M x T of the plan's in_dtype, copied
+ * before return. arrival: the request's arrival time for latency accounting
+ * (< 0: now). A frame whose input + output exceed the budget is
+ * DMAS_ERR_INVALID_ARG; full staging is DMAS_ERR_BUSY (nothing queued). */
+dmas_status_t dmas_server_submit(dmas_server_t srv, dmas_plan_t plan, const void *h_x, float in_scale,
+                                 int32_t flags, double arrival, uint64_t *ticket);
+
+/* Current record of a frame (not blocking). */
+dmas_status_t dmas_server_query(dmas_server_t srv, uint64_t ticket, dmas_frame_info_t *info);
+
+/* Block until the frame is done or failed, or timeout seconds pass
+ * (DMAS_ERR_TIMEOUT). */
+dmas_status_t dmas_server_wait(dmas_server_t srv, uint64_t ticket, double timeout, dmas_frame_info_t *info);
+
+/* Return a done frame's device memory to the arena and forget the ticket. */
+dmas_status_t dmas_server_release(dmas_server_t srv, uint64_t ticket);
+
+/* Copy a done frame's result (D x T FP32) into host memory h_out (synchronous). */
+dmas_status_t dmas_server_fetch(dmas_server_t srv, uint64_t ticket, float *h_out);
+
+/* Move up to max records of auto-released, completed frames into out
+ * (oldest first); *count receives how many. */
+dmas_status_t dmas_server_completed(dmas_server_t srv, dmas_frame_info_t *out, int32_t max, int32_t *count);
+
+/* Block until nothing is queued, admitted or in flight (or timeout). */
+dmas_status_t dmas_server_drain(dmas_server_t srv, double timeout);
+
+dmas_status_t dmas_server_stats(dmas_server_t srv, dmas_server_stats_t *stats);
+
+/* Stop the scheduler after in-flight launches finish and free everything.
+ * Unreleased results become invalid. NULL is a no-op. */
+dmas_status_t dmas_server_destroy(dmas_server_t srv);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char *dmas_last_error(void);

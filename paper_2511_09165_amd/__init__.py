@@ -5,5 +5,5 @@ The compute path is libdmas.so (hand-written HIP for gfx950, C ABI in
 include/dmas.h); this package is its Python binding.
 """
 
-from .dmas import (DTYPES, DmasError, Plan, design_lowpass, load_library,  # noqa: F401
-                   plan_for_frame, version)
+from .dmas import (DTYPES, DmasError, Plan, Server, design_lowpass, load_library,  # noqa: F401
+                   plan_for_frame, server_clock, version)

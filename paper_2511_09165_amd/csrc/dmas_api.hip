@@ -19,6 +19,7 @@
 #include "../../include/dmas.h"
 #include "dmas_internal.hpp"
 #include "dmas_kernel.hpp"
+#include "dmas_plan.hpp"
 
 namespace {
 
@@ -62,28 +63,6 @@ uint32_t spread_bits(uint32_t v)
 
 }  // namespace
 
-struct dmas_plan_s {
-    int device = 0;
-    int M = 0, T = 0, D = 0, order = 0;
-    bool cf = true, nearfield = false, linear = false, compensated = false;
-    int ng_fp64 = 0;
-    int dtype = DMAS_F32;
-    double fs = 0, c = 0;
-    float cf_eps = 0;
-    int fir_len = 0;
-    int num_tiles = 0;
-    int halo = 0;
-    int mic_block = 0;
-    int row = 0;
-    int seg_rf = 0, seg_env = 0;
-    int nseg_rf = 0, nseg_env = 0;
-    size_t lds_rf = 0, lds_env = 0;
-    int occ_rf = 0, occ_env = 0;
-    double *d_mic = nullptr;
-    double *d_dirs = nullptr;
-    int32_t *d_tiles = nullptr;
-    float *d_taps = nullptr;
-};
 
 namespace {
 
@@ -320,8 +299,39 @@ std::vector<int32_t> make_tiles(const dmas_plan_desc_t *d, bool nearfield, doubl
     return tiles;
 }
 
-hipError_t launch_dmas(int order, const dmas::KernelParams *kp, const dmas::LaunchShape &ls, hipStream_t st,
-                       int *blocks = nullptr)
+
+
+dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scale, void *stream,
+                  bool env)
+{
+    if (!plan) return fail(DMAS_ERR_INVALID_ARG, "plan is NULL");
+    if (!d_x || !d_out) return fail(DMAS_ERR_INVALID_ARG, "device pointer is NULL");
+    if (!(in_scale > 0.0f) || !std::isfinite(in_scale))
+        return fail(DMAS_ERR_INVALID_ARG, "in_scale must be finite and > 0 (got %g)", (double)in_scale);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != plan->device)
+        return fail(DMAS_ERR_INVALID_ARG, "plan belongs to device %d but device %d is current", plan->device,
+                    cur);
+    const dmas::KernelParams kp = dmas::make_params(plan, d_x, d_out, in_scale, env);
+    const dmas::LaunchShape ls = dmas::shape_of(plan, env);
+    hipError_t e = dmas::launch_plan(plan->order, &kp, ls, static_cast<hipStream_t>(stream));
+    if (e == hipErrorNotSupported)
+        return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d linear=%d comp=%d",
+                    plan->order, (int)plan->cf, (int)env, (int)plan->nearfield, (int)plan->linear,
+                    (int)plan->compensated);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DMAS_OK;
+}
+
+}  // namespace
+
+void dmas::set_last_error(const char *msg)
+{
+    g_last_error = msg ? msg : "";
+}
+
+hipError_t dmas::launch_plan(int order, const dmas::KernelParams *kp, const dmas::LaunchShape &ls, hipStream_t st,
+                             int *blocks)
 {
     switch (order) {
     case 1: return dmas::launch_order1(kp, ls, st, blocks);
@@ -335,65 +345,6 @@ hipError_t launch_dmas(int order, const dmas::KernelParams *kp, const dmas::Laun
     default: return hipErrorInvalidValue;
     }
 }
-
-dmas::LaunchShape shape_of(const dmas_plan_s *p, bool env)
-{
-    dmas::LaunchShape ls{};
-    ls.order = p->order;
-    ls.cf = p->cf;
-    ls.env = env;
-    ls.nearfield = p->nearfield;
-    ls.linear = p->linear;
-    ls.compensated = p->compensated;
-    ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
-    ls.lds_bytes = env ? p->lds_env : p->lds_rf;
-    return ls;
-}
-
-dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scale, void *stream,
-                  bool env)
-{
-    if (!plan) return fail(DMAS_ERR_INVALID_ARG, "plan is NULL");
-    if (!d_x || !d_out) return fail(DMAS_ERR_INVALID_ARG, "device pointer is NULL");
-    if (!(in_scale > 0.0f) || !std::isfinite(in_scale))
-        return fail(DMAS_ERR_INVALID_ARG, "in_scale must be finite and > 0 (got %g)", (double)in_scale);
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || cur != plan->device)
-        return fail(DMAS_ERR_INVALID_ARG, "plan belongs to device %d but device %d is current", plan->device,
-                    cur);
-    dmas::KernelParams kp{};
-    kp.x = d_x;
-    kp.out = d_out;
-    kp.mic = plan->d_mic;
-    kp.dirs = plan->d_dirs;
-    kp.tile_dirs = plan->d_tiles;
-    kp.taps = plan->d_taps;
-    kp.M = plan->M;
-    kp.T = plan->T;
-    kp.D = plan->D;
-    kp.fir_len = env ? plan->fir_len : 1;
-    kp.num_tiles = plan->num_tiles;
-    kp.seg_len = env ? plan->seg_env : plan->seg_rf;
-    kp.halo = plan->halo;
-    kp.row = plan->row;
-    kp.mic_block = plan->mic_block;
-    kp.dtype = plan->dtype;
-    kp.ng_fp64 = plan->ng_fp64;
-    kp.fs = plan->fs;
-    kp.c = plan->c;
-    kp.cf_eps = plan->cf_eps;
-    kp.in_scale = in_scale;
-    const dmas::LaunchShape ls = shape_of(plan, env);
-    hipError_t e = launch_dmas(plan->order, &kp, ls, static_cast<hipStream_t>(stream));
-    if (e == hipErrorNotSupported)
-        return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d linear=%d comp=%d",
-                    plan->order, (int)plan->cf, (int)env, (int)plan->nearfield, (int)plan->linear,
-                    (int)plan->compensated);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    return DMAS_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -555,9 +506,20 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
     const size_t ring_bytes = sizeof(float) * (size_t)W * (C + 2 * H);
     const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
-    int mb = std::min(M, dmas::kMaxMicBlock);
-    while (mb > 1 && fixed + ring_bytes + sizeof(float) * (size_t)mb * p->row > lds_cap) mb /= 2;
-    if (fixed + ring_bytes + sizeof(float) * (size_t)mb * p->row > lds_cap) {
+    // Microphones per LDS block: the largest block whose footprint lets three
+    // workgroups share a CU (else two, else one). More blocks cost barriers and
+    // delay evaluations; fewer resident workgroups cost latency hiding.
+    auto lds_for = [&](int m) { return fixed + ring_bytes + sizeof(float) * (size_t)m * p->row; };
+    const int mb_max = std::min(M, dmas::kMaxMicBlock);
+    int mb = 0;
+    for (int per_cu = 3; per_cu >= 1 && mb == 0; --per_cu)
+        for (int cand : {mb_max, 48, 32, 24, 16, 12, 8, 4, 2, 1})
+            if (cand <= mb_max && lds_for(cand) * per_cu <= lds_cap) {
+                mb = cand;
+                break;
+            }
+    if (const char *fixed_mb = std::getenv("DMAS_MIC_BLOCK")) mb = std::max(1, std::min(mb_max, std::atoi(fixed_mb)));
+    if (mb == 0 || lds_for(mb) > lds_cap) {
         plan_free(p);
         return fail(DMAS_ERR_UNSUPPORTED,
                     "direction tiles spread over %d samples: the channel window does not fit in LDS", p->halo);
@@ -569,10 +531,10 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     const char *fixed_seg = std::getenv("DMAS_SEGMENT");
     const int seg_override = fixed_seg ? std::atoi(fixed_seg) : 0;
     const int extra_env = 2 * H + (32 - (2 * H) % 32) % 32;
-    p->nseg_rf = p->nseg_env = 1;   // shape_of() needs a grid; the occupancy query ignores it
+    p->nseg_rf = p->nseg_env = 1;   // dmas::shape_of() needs a grid; the occupancy query ignores it
     for (int env = 0; env < 2; ++env) {
         int blocks = 0;
-        e = launch_dmas(n, nullptr, shape_of(p, env != 0), nullptr, &blocks);
+        e = dmas::launch_plan(n, nullptr, dmas::shape_of(p, env != 0), nullptr, &blocks);
         if (e != hipSuccess && e != hipErrorNotSupported) {
             plan_free(p);
             return hip_fail(e, "occupancy query");

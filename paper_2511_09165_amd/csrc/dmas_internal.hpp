@@ -21,6 +21,7 @@ struct KernelParams {
     const int32_t *tile_dirs; // num_tiles x dirs_per_tile direction indices (-1 = empty), device
     const float *taps;        // fir_len envelope taps, device
     int32_t M, T, D;
+    int32_t order;            // n
     int32_t fir_len;          // odd
     int32_t num_tiles;
     int32_t seg_len;          // output samples per direction per workgroup
@@ -32,6 +33,13 @@ struct KernelParams {
     double fs, c;
     float cf_eps;
     float in_scale;
+};
+
+// A batch of frames for the multi-frame kernel (device pointers).
+struct BatchParams {
+    const KernelParams *frames;   // num_frames entries
+    const int32_t *starts;        // first workgroup of each frame, ascending, starts[0] = 0
+    int32_t num_frames;
 };
 
 struct LaunchShape {
@@ -50,6 +58,19 @@ struct LaunchShape {
 constexpr int kDirsPerTile = 8;
 constexpr int kSamplesPerLane = 4;
 constexpr int kChunk = kWaveSize * kSamplesPerLane;
+
+// Batched launch over frames of order n with the given CF / envelope /
+// geometry flags (nearest delays, plain sums); grid = total workgroups.
+hipError_t launch_batch(int order, const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
+                        size_t lds_bytes, hipStream_t stream);
+hipError_t launch_batch_order1(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order2(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order3(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order4(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order5(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order6(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order7(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order8(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
 
 hipError_t launch_order1(const KernelParams *, const LaunchShape &, hipStream_t, int *);
 hipError_t launch_order2(const KernelParams *, const LaunchShape &, hipStream_t, int *);

@@ -257,19 +257,20 @@ __device__ __forceinline__ float finish_pixel(const Acc<N, CF, COMP> &acc, const
 // ---------------------------------------------------------------------------
 // The kernel.
 // ---------------------------------------------------------------------------
+// One workgroup's work: tile `tile` of directions over time segment `seg` of
+// the frame described by p. Shared by the single-frame and the multi-frame
+// (batched) kernels, so a pixel's arithmetic does not depend on how it was
+// launched.
 template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, bool COMP>
-__global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
-dmas_kernel(const KernelParams p)
+__device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile, const int seg,
+                                          float *__restrict__ smem)
 {
     constexpr int W = kDirsPerTile;
     constexpr int K = kSamplesPerLane;
     constexpr int C = kChunk;
-    extern __shared__ float smem[];
 
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
-    const int tile = blockIdx.x % p.num_tiles;   // segment-major: concurrent workgroups share a time window
-    const int seg = blockIdx.x / p.num_tiles;
 
     const int H = ENV ? (p.fir_len - 1) / 2 : 0;
     const int ring_len = C + 2 * H;
@@ -281,7 +282,6 @@ dmas_kernel(const KernelParams p)
     const int dir0 = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W]);
     const bool active = dir >= 0;
     const double *vdir = p.dirs + 3 * (active ? dir : dir0);
-    const double *vref = p.dirs + 3 * dir0;
 
     // Output blocks of a chunk start at tc - H (envelope) or tc (RF). seg_len is
     // a multiple of 32 and the envelope start is pulled back by align_shift so
@@ -295,25 +295,29 @@ dmas_kernel(const KernelParams p)
     const int nblocks = (p.M + p.mic_block - 1) / p.mic_block;
     const int two_halo = 2 * p.halo;
 
-    // Lane i of every wave holds the LDS offset (and fraction) of microphone
-    // i of the current block for this wave's direction.
+    // Per block of microphones: lane i of every wave computes its direction's
+    // delay for microphone i of the block; wave 0's direction is the tile's
+    // reference, so wave 0 publishes its delays for the staging step. After a
+    // barrier each lane turns (delay - reference delay) into its LDS offset.
+    int mydw = 0;
     int myoff = 0;
     float myfrac = 0.0f;
     auto block_geometry = [&](int blk) {
         const int mic = blk * p.mic_block + lane;
         if (lane < p.mic_block) {
-            int rel = 0;
             if (mic < p.M) {
-                const double *r = p.mic + 3 * mic;
-                float f0, fw;
-                const int d0 = steer_whole<NEAR, LINEAR>(r, vref, p.fs, p.c, &f0);
-                const int dw = steer_whole<NEAR, LINEAR>(r, vdir, p.fs, p.c, &fw);
-                if (wave == 0) dref_lds[lane] = d0;
-                rel = min(max(dw - d0 + p.halo, 0), two_halo);  // the host bound keeps this in range
-                myfrac = fw;
+                mydw = steer_whole<NEAR, LINEAR>(p.mic + 3 * mic, vdir, p.fs, p.c, &myfrac);
+                if (wave == 0) dref_lds[lane] = mydw;
             } else if (wave == 0) {
                 dref_lds[lane] = 0;
             }
+        }
+    };
+    auto block_offsets = [&](int blk) {
+        if (lane < p.mic_block) {
+            int rel = 0;
+            if (blk * p.mic_block + lane < p.M)
+                rel = min(max(mydw - dref_lds[lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
             myoff = lane * p.row + rel;
         }
     };
@@ -335,6 +339,7 @@ dmas_kernel(const KernelParams p)
         for (int blk = 0; blk < nblocks; ++blk) {
             if (nblocks > 1) block_geometry(blk);
             __syncthreads();  // reference delays visible; previous block's reads done
+            block_offsets(blk);
             // ---- stage this block's channel windows into LDS ----
             for (int i = wave; i < p.mic_block; i += W) {
                 const int mic = blk * p.mic_block + i;
@@ -428,6 +433,37 @@ dmas_kernel(const KernelParams p)
     }
 }
 
+// Single-frame kernel: workgroup b covers tile b % num_tiles of segment
+// b / num_tiles (tiles fastest, so workgroups resident at the same time share
+// a time window of the channels).
+template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, bool COMP>
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
+dmas_kernel(const KernelParams p)
+{
+    extern __shared__ float smem[];
+    dmas_body<N, CF, ENV, NEAR, LINEAR, COMP>(p, blockIdx.x % p.num_tiles, blockIdx.x / p.num_tiles, smem);
+}
+
+// Multi-frame kernel for the serving runtime: the batch lists the frames'
+// parameters (all of order N) and the first workgroup index of each frame
+// (ascending); each workgroup finds its frame by binary search.
+template <int N, bool CF, bool ENV, bool NEAR>
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
+dmas_batch_kernel(const BatchParams bp)
+{
+    extern __shared__ float smem[];
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = bp.num_frames - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bp.starts[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const KernelParams p = bp.frames[lo];
+    const int local = b - bp.starts[lo];
+    dmas_body<N, CF, ENV, NEAR, false, false>(p, local % p.num_tiles, local / p.num_tiles, smem);
+}
+
 // Host-side launcher for one order: picks the instantiation for the flags.
 // Instantiated: every (CF, envelope, geometry) with nearest delays; linear
 // delays with CF; compensated sums for the far field with CF.
@@ -454,6 +490,37 @@ hipError_t occupancy_one(const LaunchShape &s, int *blocks)
     auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, COMP>;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(fn),
                                                         kDirsPerTile * kWaveSize, s.lds_bytes);
+}
+
+template <int N, bool CF, bool ENV, bool NEAR>
+hipError_t launch_batch_one(const BatchParams &bp, unsigned grid, size_t lds, hipStream_t stream)
+{
+    auto fn = dmas_batch_kernel<N, CF, ENV, NEAR>;
+    static size_t lds_set = 64 * 1024;
+    if (lds > lds_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kDirsPerTile * kWaveSize), lds, stream, bp);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_batch_order(const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
+                              size_t lds, hipStream_t stream)
+{
+    if (cf) {
+        if (env) return nearfield ? launch_batch_one<N, true, true, true>(bp, grid, lds, stream)
+                                  : launch_batch_one<N, true, true, false>(bp, grid, lds, stream);
+        return nearfield ? launch_batch_one<N, true, false, true>(bp, grid, lds, stream)
+                         : launch_batch_one<N, true, false, false>(bp, grid, lds, stream);
+    }
+    if (env) return nearfield ? launch_batch_one<N, false, true, true>(bp, grid, lds, stream)
+                              : launch_batch_one<N, false, true, false>(bp, grid, lds, stream);
+    return nearfield ? launch_batch_one<N, false, false, true>(bp, grid, lds, stream)
+                     : launch_batch_one<N, false, false, false>(bp, grid, lds, stream);
 }
 
 template <int N>

@@ -1,5 +1,5 @@
-// Kernel instantiations for DMAS order n = 6 (one order per unit so that the
-// orders compile in parallel).
+// Kernel instantiations for DMAS order n = 6, single-frame and multi-frame (one
+// order per unit so that the orders compile in parallel).
 #include "dmas_kernel.hpp"
 
 namespace dmas {
@@ -8,5 +8,11 @@ namespace dmas {
 hipError_t launch_order6(const KernelParams *p, const LaunchShape &s, hipStream_t stream, int *blocks)
 {
     return launch_order<6>(p, s, stream, blocks);
+}
+
+hipError_t launch_batch_order6(const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
+                               size_t lds, hipStream_t stream)
+{
+    return launch_batch_order<6>(bp, cf, env, nearfield, grid, lds, stream);
 }
 }  // namespace dmas

@@ -1,0 +1,93 @@
+// Internal: the plan object behind dmas_plan_t, and helpers shared by the
+// host API (dmas_api.hip) and the serving runtime (dmas_server.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "dmas_internal.hpp"
+
+struct dmas_plan_s {
+    int device = 0;
+    int M = 0, T = 0, D = 0, order = 0;
+    bool cf = true, nearfield = false, linear = false, compensated = false;
+    int ng_fp64 = 0;
+    int dtype = DMAS_F32;
+    double fs = 0, c = 0;
+    float cf_eps = 0;
+    int fir_len = 0;
+    int num_tiles = 0;
+    int halo = 0;
+    int mic_block = 0;
+    int row = 0;
+    int seg_rf = 0, seg_env = 0;
+    int nseg_rf = 0, nseg_env = 0;
+    size_t lds_rf = 0, lds_env = 0;
+    int occ_rf = 0, occ_env = 0;
+    double *d_mic = nullptr;
+    double *d_dirs = nullptr;
+    int32_t *d_tiles = nullptr;
+    float *d_taps = nullptr;
+};
+
+namespace dmas {
+
+// Kernel arguments for one launch of `plan` on input d_x / output d_out.
+inline KernelParams make_params(const dmas_plan_s *plan, const void *d_x, float *d_out, float in_scale, bool env)
+{
+    KernelParams kp{};
+    kp.x = d_x;
+    kp.out = d_out;
+    kp.mic = plan->d_mic;
+    kp.dirs = plan->d_dirs;
+    kp.tile_dirs = plan->d_tiles;
+    kp.taps = plan->d_taps;
+    kp.M = plan->M;
+    kp.T = plan->T;
+    kp.D = plan->D;
+    kp.order = plan->order;
+    kp.fir_len = env ? plan->fir_len : 1;
+    kp.num_tiles = plan->num_tiles;
+    kp.seg_len = env ? plan->seg_env : plan->seg_rf;
+    kp.halo = plan->halo;
+    kp.row = plan->row;
+    kp.mic_block = plan->mic_block;
+    kp.dtype = plan->dtype;
+    kp.ng_fp64 = plan->ng_fp64;
+    kp.fs = plan->fs;
+    kp.c = plan->c;
+    kp.cf_eps = plan->cf_eps;
+    kp.in_scale = in_scale;
+    return kp;
+}
+
+inline LaunchShape shape_of(const dmas_plan_s *p, bool env)
+{
+    LaunchShape ls{};
+    ls.order = p->order;
+    ls.cf = p->cf;
+    ls.env = env;
+    ls.nearfield = p->nearfield;
+    ls.linear = p->linear;
+    ls.compensated = p->compensated;
+    ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
+    ls.lds_bytes = env ? p->lds_env : p->lds_rf;
+    return ls;
+}
+
+// Workgroups of one launch of the plan.
+inline int64_t plan_workgroups(const dmas_plan_s *p, bool env)
+{
+    return (int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf);
+}
+
+// Record the calling thread's last error message (returned by dmas_last_error).
+void set_last_error(const char *msg);
+
+// Launch one plan (order dispatch); with kp == nullptr, report occupancy in *blocks.
+hipError_t launch_plan(int order, const KernelParams *kp, const LaunchShape &ls, hipStream_t st,
+                       int *blocks = nullptr);
+
+}  // namespace dmas

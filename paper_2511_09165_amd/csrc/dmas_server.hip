@@ -1,0 +1,672 @@
+// Serving runtime behind the dmas_server_* entry points of include/dmas.h:
+// admission by an HBM budget, pinned staging, asynchronous input copies and
+// continuous batching of heterogeneous frames into multi-frame launches on
+// several streams. Host C++ only; the device work is dmas_batch_kernel /
+// dmas_kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dmas.h"
+#include "dmas_internal.hpp"
+#include "dmas_plan.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxBatchFrames = 1024;
+
+size_t align_up(size_t v)
+{
+    return (v + kAlign - 1) & ~(kAlign - 1);
+}
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+public:
+    void reset(size_t size)
+    {
+        free_.clear();
+        if (size) free_[0] = size;
+        size_ = size;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align_up(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+enum FrameState { kQueued = 0, kAdmitted = 1, kLaunched = 2, kDone = 3, kFailed = -1 };
+
+struct Frame {
+    uint64_t ticket = 0;
+    dmas_plan_s *plan = nullptr;
+    float in_scale = 1.0f;
+    bool env = false, auto_release = false;
+    size_t in_bytes = 0, out_bytes = 0;
+    size_t stage_off = 0;
+    bool staged = false;
+    size_t in_off = 0, out_off = 0;
+    bool on_device = false;
+    hipEvent_t copied = nullptr;
+    int state = kQueued;
+    int batch_frames = 0;
+    double t_arrival = 0, t_admit = 0, t_launch = 0, t_done = 0;
+};
+
+struct Launch {
+    std::vector<Frame *> frames;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+};
+
+size_t elem_size(int dtype)
+{
+    return dtype == DMAS_F32 ? 4 : 2;
+}
+
+// Frames that the multi-frame kernel serves (nearest delays, plain sums).
+bool batchable(const dmas_plan_s *p)
+{
+    return !p->linear && !p->compensated;
+}
+
+// Frames that can share one multi-frame launch (same kernel instantiation).
+bool same_class(const Frame *a, const Frame *b)
+{
+    return a->env == b->env && a->plan->order == b->plan->order && a->plan->cf == b->plan->cf &&
+           a->plan->nearfield == b->plan->nearfield;
+}
+
+dmas_status_t srv_fail(dmas_status_t st, const char *msg)
+{
+    dmas::set_last_error(msg);
+    return st;
+}
+
+}  // namespace
+
+struct dmas_server_s {
+    int device = 0;
+    size_t budget = 0, staging = 0;
+    int nstreams = 2, max_batch = 64;
+    int64_t batch_wg_cap = 0;   // workgroups per multi-frame launch (about two device rounds)
+    char *d_arena = nullptr;
+    char *h_staging = nullptr;
+    Arena arena, stage_arena;
+    size_t hbm_peak = 0;
+    hipStream_t copy_stream = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<Launch> launches;
+    std::vector<char *> d_tables, h_tables;
+    size_t table_bytes = 0;
+    std::vector<hipEvent_t> event_pool;
+
+    std::deque<Frame *> queued, admitted;
+    std::unordered_map<uint64_t, Frame *> frames;
+    std::deque<dmas_frame_info_t> finished;   // records of auto-released frames
+    uint64_t next_ticket = 1;
+    int64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_launches = 0, n_batched = 0;
+
+    std::mutex mu;
+    std::condition_variable cv_done;     // frame completions, for waiters
+    std::condition_variable cv_work;     // new submissions, for the scheduler
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    std::string worker_error;
+
+    hipEvent_t get_event()
+    {
+        if (!event_pool.empty()) {
+            hipEvent_t e = event_pool.back();
+            event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    }
+
+    void fill_info(const Frame *f, dmas_frame_info_t *info) const
+    {
+        info->ticket = f->ticket;
+        info->state = f->state;
+        info->batch_frames = f->batch_frames;
+        info->t_arrival = f->t_arrival;
+        info->t_admit = f->t_admit;
+        info->t_launch = f->t_launch;
+        info->t_done = f->t_done;
+        info->d_out = (f->on_device && f->state == kDone) ? reinterpret_cast<float *>(d_arena + f->out_off) : nullptr;
+        info->pixels = (int64_t)f->plan->D * f->plan->T;
+    }
+
+    void free_device(Frame *f)
+    {
+        if (!f->on_device) return;
+        arena.release(f->in_off, f->in_bytes);
+        arena.release(f->out_off, f->out_bytes);
+        f->on_device = false;
+    }
+
+    void free_staging(Frame *f)
+    {
+        if (!f->staged) return;
+        stage_arena.release(f->stage_off, f->in_bytes);
+        f->staged = false;
+    }
+
+    // ---- scheduler steps (called with mu held) ----
+    bool collect_completions()
+    {
+        bool progress = false;
+        for (auto &l : launches) {
+            if (!l.busy) continue;
+            hipError_t q = hipEventQuery(l.done);
+            if (q == hipErrorNotReady) continue;
+            const double t = now_s();
+            for (Frame *f : l.frames) {
+                f->t_done = t;
+                f->state = (q == hipSuccess) ? kDone : kFailed;
+                free_staging(f);
+                if (f->copied) event_pool.push_back(f->copied), f->copied = nullptr;
+                if (q == hipSuccess) ++n_completed; else ++n_failed;
+                if (f->auto_release || q != hipSuccess) {
+                    free_device(f);
+                    if (f->auto_release) {
+                        dmas_frame_info_t info;
+                        fill_info(f, &info);
+                        finished.push_back(info);
+                        frames.erase(f->ticket);
+                        delete f;
+                    }
+                }
+            }
+            if (q != hipSuccess) worker_error = hipGetErrorString(q);
+            l.frames.clear();
+            l.busy = false;
+            progress = true;
+        }
+        if (progress) cv_done.notify_all();
+        return progress;
+    }
+
+    bool admit()
+    {
+        bool progress = false;
+        while (!queued.empty()) {
+            Frame *f = queued.front();
+            size_t in_off, out_off;
+            if (!arena.alloc(f->in_bytes, &in_off)) break;
+            if (!arena.alloc(f->out_bytes, &out_off)) {
+                arena.release(in_off, f->in_bytes);
+                break;
+            }
+            f->in_off = in_off;
+            f->out_off = out_off;
+            f->on_device = true;
+            hbm_peak = std::max(hbm_peak, arena.used());
+            f->copied = get_event();
+            hipError_t e = hipMemcpyAsync(d_arena + in_off, h_staging + f->stage_off, f->in_bytes,
+                                          hipMemcpyHostToDevice, copy_stream);
+            if (e == hipSuccess && f->copied) e = hipEventRecord(f->copied, copy_stream);
+            f->t_admit = now_s();
+            queued.pop_front();
+            if (e != hipSuccess || !f->copied) {
+                f->state = kFailed;
+                ++n_failed;
+                free_device(f);
+                free_staging(f);
+                worker_error = "input copy failed";
+                cv_done.notify_all();
+            } else {
+                f->state = kAdmitted;
+                admitted.push_back(f);
+            }
+            progress = true;
+        }
+        return progress;
+    }
+
+    bool launch()
+    {
+        bool progress = false;
+        while (!admitted.empty()) {
+            int s = -1;
+            for (int i = 0; i < nstreams; ++i)
+                if (!launches[i].busy) {
+                    s = i;
+                    break;
+                }
+            if (s < 0) break;
+            Launch &l = launches[s];
+            hipStream_t st = streams[s];
+            Frame *head = admitted.front();
+            std::vector<Frame *> group;
+            // Frames that fill the device by themselves go alone; smaller frames of
+            // the same kernel class are packed, in arrival order, up to about two
+            // device rounds of workgroups.
+            const int64_t head_wgs = dmas::plan_workgroups(head->plan, head->env);
+            if (max_batch > 1 && batchable(head->plan) && head_wgs < batch_wg_cap) {
+                int64_t wgs = 0;
+                for (auto it = admitted.begin(); it != admitted.end() && (int)group.size() < max_batch;) {
+                    Frame *f = *it;
+                    const int64_t fw = dmas::plan_workgroups(f->plan, f->env);
+                    if (batchable(f->plan) && same_class(head, f) && (group.empty() || wgs + fw <= batch_wg_cap)) {
+                        group.push_back(f);
+                        wgs += fw;
+                        it = admitted.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            } else {
+                group.push_back(head);
+                admitted.pop_front();
+            }
+            hipError_t e = hipSuccess;
+            for (Frame *f : group)
+                if (e == hipSuccess) e = hipStreamWaitEvent(st, f->copied, 0);
+            if (e == hipSuccess) {
+                if (group.size() == 1) {
+                    Frame *f = group[0];
+                    const dmas::KernelParams kp = dmas::make_params(
+                        f->plan, d_arena + f->in_off, reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale, f->env);
+                    e = dmas::launch_plan(f->plan->order, &kp, dmas::shape_of(f->plan, f->env), st);
+                } else {
+                    // Table layout: nf KernelParams, then nf int32 first-workgroup indices.
+                    const int nf = (int)group.size();
+                    auto *kp = reinterpret_cast<dmas::KernelParams *>(h_tables[s]);
+                    auto *starts = reinterpret_cast<int32_t *>(h_tables[s] + sizeof(dmas::KernelParams) * nf);
+                    int64_t total = 0;
+                    size_t lds = 0;
+                    for (int i = 0; i < nf; ++i) {
+                        Frame *f = group[i];
+                        kp[i] = dmas::make_params(f->plan, d_arena + f->in_off,
+                                                  reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale, f->env);
+                        starts[i] = (int32_t)total;
+                        total += dmas::plan_workgroups(f->plan, f->env);
+                        lds = std::max(lds, f->env ? f->plan->lds_env : f->plan->lds_rf);
+                    }
+                    if (total > INT32_MAX) {
+                        e = hipErrorInvalidValue;
+                    } else {
+                        const size_t used = (sizeof(dmas::KernelParams) + sizeof(int32_t)) * nf;
+                        e = hipMemcpyAsync(d_tables[s], h_tables[s], used, hipMemcpyHostToDevice, st);
+                        if (e == hipSuccess) {
+                            dmas::BatchParams bp;
+                            bp.frames = reinterpret_cast<const dmas::KernelParams *>(d_tables[s]);
+                            bp.starts = reinterpret_cast<const int32_t *>(d_tables[s] + sizeof(dmas::KernelParams) * nf);
+                            bp.num_frames = nf;
+                            e = dmas::launch_batch(head->plan->order, bp, head->plan->cf, head->env,
+                                                   head->plan->nearfield, (unsigned)total, lds, st);
+                        }
+                    }
+                }
+            }
+            if (e == hipSuccess) e = hipEventRecord(l.done, st);
+            const double t = now_s();
+            ++n_launches;
+            if (group.size() > 1) n_batched += (int64_t)group.size();
+            for (Frame *f : group) {
+                f->t_launch = t;
+                f->batch_frames = (int)group.size();
+                f->state = kLaunched;
+            }
+            l.frames = group;
+            l.busy = true;
+            if (e != hipSuccess) {
+                // The launch did not happen: fail its frames now (their event may never fire).
+                worker_error = hipGetErrorString(e);
+                hipError_t sync = hipStreamSynchronize(st);
+                (void)sync;
+                for (Frame *f : group) {
+                    f->state = kFailed;
+                    f->t_done = now_s();
+                    ++n_failed;
+                    free_staging(f);
+                    free_device(f);
+                }
+                l.frames.clear();
+                l.busy = false;
+                cv_done.notify_all();
+            }
+            progress = true;
+        }
+        return progress;
+    }
+
+    void run()
+    {
+        hipSetDevice(device);
+        std::unique_lock<std::mutex> lk(mu);
+        while (!stop.load()) {
+            bool progress = collect_completions();
+            progress |= admit();
+            progress |= launch();
+            bool busy = false;
+            for (auto &l : launches) busy |= l.busy;
+            if (!progress) {
+                if (!busy && queued.empty() && admitted.empty()) {
+                    cv_work.wait_for(lk, std::chrono::milliseconds(5));
+                } else {
+                    lk.unlock();
+                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                    lk.lock();
+                }
+            }
+        }
+    }
+};
+
+extern "C" {
+
+double dmas_server_clock(void)
+{
+    return now_s();
+}
+
+dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out)
+{
+    if (!d || !out) return srv_fail(DMAS_ERR_INVALID_ARG, "desc or out is NULL");
+    *out = nullptr;
+    if (d->hbm_budget_bytes <= 0) return srv_fail(DMAS_ERR_INVALID_ARG, "hbm_budget_bytes must be > 0");
+    if (d->staging_bytes < 0 || d->num_streams < 0 || d->max_batch_frames < 0)
+        return srv_fail(DMAS_ERR_INVALID_ARG, "negative server parameter");
+    if (d->max_batch_frames > kMaxBatchFrames) return srv_fail(DMAS_ERR_INVALID_ARG, "max_batch_frames > 1024");
+    if (d->num_streams > 16) return srv_fail(DMAS_ERR_INVALID_ARG, "num_streams > 16");
+    auto *s = new (std::nothrow) dmas_server_s();
+    if (!s) return srv_fail(DMAS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    hipGetDevice(&s->device);
+    s->budget = align_up((size_t)d->hbm_budget_bytes);
+    s->staging = align_up(d->staging_bytes ? (size_t)d->staging_bytes : (size_t)256 << 20);
+    s->nstreams = d->num_streams ? d->num_streams : 2;
+    s->max_batch = d->max_batch_frames ? d->max_batch_frames : 64;
+    {
+        hipDeviceProp_t prop;
+        int cus = 256;
+        if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) cus = prop.multiProcessorCount;
+        s->batch_wg_cap = (int64_t)2 * 3 * cus;
+    }
+    auto fail_all = [&](hipError_t e, const char *what) {
+        dmas_server_destroy(s);
+        dmas::set_last_error((std::string(what) + ": " + hipGetErrorString(e)).c_str());
+        return e == hipErrorOutOfMemory ? DMAS_ERR_OUT_OF_MEMORY : DMAS_ERR_DEVICE;
+    };
+    hipError_t e = hipMalloc(&s->d_arena, s->budget);
+    if (e != hipSuccess) return fail_all(e, "HBM arena");
+    e = hipHostMalloc(&s->h_staging, s->staging, hipHostMallocDefault);
+    if (e != hipSuccess) return fail_all(e, "pinned staging");
+    s->arena.reset(s->budget);
+    s->stage_arena.reset(s->staging);
+    e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail_all(e, "copy stream");
+    s->table_bytes = align_up((sizeof(dmas::KernelParams) + sizeof(int32_t)) * kMaxBatchFrames);
+    s->streams.resize(s->nstreams, nullptr);
+    s->launches.resize(s->nstreams);
+    s->d_tables.resize(s->nstreams, nullptr);
+    s->h_tables.resize(s->nstreams, nullptr);
+    for (int i = 0; i < s->nstreams; ++i) {
+        if ((e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking)) != hipSuccess)
+            return fail_all(e, "compute stream");
+        if ((e = hipEventCreateWithFlags(&s->launches[i].done, hipEventDisableTiming)) != hipSuccess)
+            return fail_all(e, "event");
+        if ((e = hipMalloc(&s->d_tables[i], s->table_bytes)) != hipSuccess) return fail_all(e, "batch table");
+        if ((e = hipHostMalloc(&s->h_tables[i], s->table_bytes, hipHostMallocDefault)) != hipSuccess)
+            return fail_all(e, "batch table (host)");
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_submit(dmas_server_t s, dmas_plan_t plan, const void *h_x, float in_scale, int32_t flags,
+                                 double arrival, uint64_t *ticket)
+{
+    if (!s || !plan || !h_x || !ticket) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL argument");
+    if (!(in_scale > 0.0f) || !std::isfinite(in_scale)) return srv_fail(DMAS_ERR_INVALID_ARG, "in_scale must be > 0");
+    if (flags & ~(DMAS_SUBMIT_ENVELOPE | DMAS_SUBMIT_AUTO_RELEASE)) return srv_fail(DMAS_ERR_INVALID_ARG, "unknown flags");
+    if (plan->device != s->device) return srv_fail(DMAS_ERR_INVALID_ARG, "plan and server are on different devices");
+    auto *f = new (std::nothrow) Frame();
+    if (!f) return srv_fail(DMAS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    f->plan = plan;
+    f->in_scale = in_scale;
+    f->env = (flags & DMAS_SUBMIT_ENVELOPE) != 0;
+    f->auto_release = (flags & DMAS_SUBMIT_AUTO_RELEASE) != 0;
+    f->in_bytes = (size_t)plan->M * plan->T * elem_size(plan->dtype);
+    f->out_bytes = (size_t)plan->D * plan->T * sizeof(float);
+    if (align_up(f->in_bytes) + align_up(f->out_bytes) > s->budget) {
+        delete f;
+        return srv_fail(DMAS_ERR_INVALID_ARG, "frame input + output exceed the server's HBM budget");
+    }
+    if (align_up(f->in_bytes) > s->staging) {
+        delete f;
+        return srv_fail(DMAS_ERR_INVALID_ARG, "frame input exceeds the server's staging memory");
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->stage_arena.alloc(f->in_bytes, &f->stage_off)) {
+            delete f;
+            return srv_fail(DMAS_ERR_BUSY, "staging memory full");
+        }
+        f->staged = true;
+    }
+    // The staging range is reserved for this frame: copy outside the lock.
+    std::memcpy(s->h_staging + f->stage_off, h_x, f->in_bytes);
+    const double t = now_s();
+    f->t_arrival = arrival >= 0 ? arrival : t;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        f->ticket = s->next_ticket++;
+        s->frames[f->ticket] = f;
+        s->queued.push_back(f);
+        ++s->n_submitted;
+        *ticket = f->ticket;
+    }
+    s->cv_work.notify_one();
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_query(dmas_server_t s, uint64_t ticket, dmas_frame_info_t *info)
+{
+    if (!s || !info) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->frames.find(ticket);
+    if (it == s->frames.end()) return srv_fail(DMAS_ERR_INVALID_ARG, "unknown ticket");
+    s->fill_info(it->second, info);
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_wait(dmas_server_t s, uint64_t ticket, double timeout, dmas_frame_info_t *info)
+{
+    if (!s) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout);
+    while (true) {
+        auto it = s->frames.find(ticket);
+        if (it == s->frames.end()) return srv_fail(DMAS_ERR_INVALID_ARG, "unknown ticket");
+        Frame *f = it->second;
+        if (f->state == kDone || f->state == kFailed) {
+            if (info) s->fill_info(f, info);
+            return f->state == kDone ? DMAS_OK : srv_fail(DMAS_ERR_DEVICE, "frame failed");
+        }
+        if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            auto it2 = s->frames.find(ticket);
+            if (it2 != s->frames.end() && (it2->second->state == kDone || it2->second->state == kFailed)) continue;
+            return srv_fail(DMAS_ERR_TIMEOUT, "timed out waiting for the frame");
+        }
+    }
+}
+
+dmas_status_t dmas_server_release(dmas_server_t s, uint64_t ticket)
+{
+    if (!s) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->frames.find(ticket);
+    if (it == s->frames.end()) return srv_fail(DMAS_ERR_INVALID_ARG, "unknown ticket");
+    Frame *f = it->second;
+    if (f->state != kDone && f->state != kFailed)
+        return srv_fail(DMAS_ERR_INVALID_ARG, "frame is not finished; wait for it before releasing");
+    s->free_device(f);
+    s->free_staging(f);
+    s->frames.erase(it);
+    delete f;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_fetch(dmas_server_t s, uint64_t ticket, float *h_out)
+{
+    if (!s || !h_out) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL argument");
+    const float *src = nullptr;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->frames.find(ticket);
+        if (it == s->frames.end()) return srv_fail(DMAS_ERR_INVALID_ARG, "unknown ticket");
+        Frame *f = it->second;
+        if (f->state != kDone || !f->on_device) return srv_fail(DMAS_ERR_INVALID_ARG, "frame has no result");
+        src = reinterpret_cast<const float *>(s->d_arena + f->out_off);
+        bytes = f->out_bytes;
+    }
+    // The result stays allocated until the caller releases the ticket.
+    hipError_t e = hipMemcpy(h_out, src, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return srv_fail(DMAS_ERR_DEVICE, hipGetErrorString(e));
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_completed(dmas_server_t s, dmas_frame_info_t *out, int32_t max, int32_t *count)
+{
+    if (!s || !count || (max > 0 && !out)) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t n = 0;
+    while (n < max && !s->finished.empty()) {
+        out[n++] = s->finished.front();
+        s->finished.pop_front();
+    }
+    *count = n;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_drain(dmas_server_t s, double timeout)
+{
+    if (!s) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout);
+    while (true) {
+        bool busy = !s->queued.empty() || !s->admitted.empty();
+        for (auto &l : s->launches) busy |= l.busy;
+        if (!busy) return DMAS_OK;
+        if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            busy = !s->queued.empty() || !s->admitted.empty();
+            for (auto &l : s->launches) busy |= l.busy;
+            if (!busy) return DMAS_OK;
+            return srv_fail(DMAS_ERR_TIMEOUT, "timed out draining the server");
+        }
+    }
+}
+
+dmas_status_t dmas_server_stats(dmas_server_t s, dmas_server_stats_t *st)
+{
+    if (!s || !st) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    st->submitted = s->n_submitted;
+    st->completed = s->n_completed;
+    st->failed = s->n_failed;
+    st->launches = s->n_launches;
+    st->batched_frames = s->n_batched;
+    st->queued = (int64_t)s->queued.size();
+    st->admitted_not_launched = (int64_t)s->admitted.size();
+    int64_t inflight = 0;
+    for (auto &l : s->launches) inflight += (int64_t)l.frames.size();
+    st->in_flight = inflight;
+    st->hbm_in_use = (int64_t)s->arena.used();
+    st->hbm_peak = (int64_t)s->hbm_peak;
+    st->hbm_budget = (int64_t)s->budget;
+    return DMAS_OK;
+}
+
+dmas_status_t dmas_server_destroy(dmas_server_t s)
+{
+    if (!s) return DMAS_OK;
+    if (s->worker.joinable()) {
+        s->stop.store(true);
+        s->cv_work.notify_all();
+        s->worker.join();
+    }
+    for (hipStream_t st : s->streams)
+        if (st) hipStreamSynchronize(st);
+    if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
+    for (auto &kv : s->frames) {
+        if (kv.second->copied) hipEventDestroy(kv.second->copied);
+        delete kv.second;
+    }
+    for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
+    for (auto &l : s->launches)
+        if (l.done) hipEventDestroy(l.done);
+    for (hipStream_t st : s->streams)
+        if (st) hipStreamDestroy(st);
+    if (s->copy_stream) hipStreamDestroy(s->copy_stream);
+    for (char *p : s->d_tables) hipFree(p);
+    for (char *p : s->h_tables) hipHostFree(p);
+    hipFree(s->d_arena);
+    hipHostFree(s->h_staging);
+    delete s;
+    return DMAS_OK;
+}
+
+}  // extern "C"

@@ -18,11 +18,16 @@ LIB_PATH = os.path.join(_HERE, "libdmas.so")
 
 DMAS_OK = 0
 STATUS_NAMES = {0: "DMAS_OK", 1: "DMAS_ERR_INVALID_ARG", 2: "DMAS_ERR_UNSUPPORTED",
-                3: "DMAS_ERR_OUT_OF_MEMORY", 4: "DMAS_ERR_DEVICE"}
+                3: "DMAS_ERR_OUT_OF_MEMORY", 4: "DMAS_ERR_DEVICE", 5: "DMAS_ERR_BUSY", 6: "DMAS_ERR_TIMEOUT"}
+SUBMIT_ENVELOPE = 1
+SUBMIT_AUTO_RELEASE = 2
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTED = ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
             "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass",
-            "dmas_last_error", "dmas_version")
+            "dmas_last_error", "dmas_version",
+            "dmas_server_clock", "dmas_server_create", "dmas_server_submit", "dmas_server_query",
+            "dmas_server_wait", "dmas_server_release", "dmas_server_fetch", "dmas_server_completed",
+            "dmas_server_drain", "dmas_server_stats", "dmas_server_destroy")
 
 
 class DmasError(RuntimeError):
@@ -50,6 +55,26 @@ class PlanInfo(ctypes.Structure):
     _fields_ += [("workgroups", ctypes.c_int64)]
 
 
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("staging_bytes", ctypes.c_int64),
+                ("num_streams", ctypes.c_int32), ("max_batch_frames", ctypes.c_int32)]
+
+
+class FrameInfo(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("state", ctypes.c_int32), ("batch_frames", ctypes.c_int32),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("d_out", ctypes.c_void_p), ("pixels", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "submitted", "completed", "failed", "launches", "batched_frames", "queued", "admitted_not_launched",
+        "in_flight", "hbm_in_use", "hbm_peak", "hbm_budget")]
+
+
 _lib = None
 
 
@@ -75,6 +100,23 @@ def load_library(path: Optional[str] = None):
                                         ctypes.POINTER(ctypes.c_float)]
     for name in ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
                  "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass"):
+        getattr(lib, name).restype = st
+    lib.dmas_server_clock.restype = ctypes.c_double
+    lib.dmas_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)]
+    lib.dmas_server_submit.argtypes = [vp, vp, vp, ctypes.c_float, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+    lib.dmas_server_query.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(FrameInfo)]
+    lib.dmas_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(FrameInfo)]
+    lib.dmas_server_release.argtypes = [vp, ctypes.c_uint64]
+    lib.dmas_server_fetch.argtypes = [vp, ctypes.c_uint64, vp]
+    lib.dmas_server_completed.argtypes = [vp, ctypes.POINTER(FrameInfo), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
+    lib.dmas_server_drain.argtypes = [vp, ctypes.c_double]
+    lib.dmas_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.dmas_server_destroy.argtypes = [vp]
+    for name in ("dmas_server_create", "dmas_server_submit", "dmas_server_query", "dmas_server_wait",
+                 "dmas_server_release", "dmas_server_fetch", "dmas_server_completed", "dmas_server_drain",
+                 "dmas_server_stats", "dmas_server_destroy"):
         getattr(lib, name).restype = st
     lib.dmas_last_error.restype = ctypes.c_char_p
     lib.dmas_version.restype = ctypes.c_char_p
@@ -230,3 +272,87 @@ def plan_for_frame(frame, **kw) -> Plan:
                 fs=frame.fs, c=frame.c, use_cf=frame.use_cf, nearfield=frame.nearfield)
     args.update(kw)
     return Plan(**args)
+
+
+def server_clock() -> float:
+    return float(load_library().dmas_server_clock())
+
+
+class Server:
+    """Continuous-batching request loop on the current device (dmas_server_* in include/dmas.h).
+
+    ``hbm_budget`` bytes of device memory hold admitted frames' inputs and
+    outputs; frames are queued by ``submit`` and launched in multi-frame
+    batches of up to ``max_batch`` on ``num_streams`` streams
+    (``max_batch=1, num_streams=1`` gives one plain launch per frame).
+    """
+
+    def __init__(self, hbm_budget: int, staging: int = 0, num_streams: int = 2, max_batch: int = 64):
+        self._lib = load_library()
+        d = ServerDesc(int(hbm_budget), int(staging), int(num_streams), int(max_batch))
+        self._h = ctypes.c_void_p()
+        _check(self._lib.dmas_server_create(ctypes.byref(d), ctypes.byref(self._h)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dmas_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, plan: Plan, x: np.ndarray, in_scale: float = 1.0, envelope: bool = True,
+               auto_release: bool = False, arrival: float = -1.0) -> int:
+        """Queue a frame (host array of the plan's dtype, shape (M, T)); returns its ticket."""
+        want = {"f32": np.float32, "f16": np.float16, "bf16": np.uint16}[plan.in_dtype]
+        xa = np.ascontiguousarray(x)
+        if xa.dtype != want or xa.shape != (plan.num_mics, plan.num_samples):
+            raise ValueError(f"x must be a contiguous {np.dtype(want)} array of shape "
+                             f"({plan.num_mics}, {plan.num_samples})")
+        flags = (SUBMIT_ENVELOPE if envelope else 0) | (SUBMIT_AUTO_RELEASE if auto_release else 0)
+        t = ctypes.c_uint64()
+        _check(self._lib.dmas_server_submit(self._h, ctypes.c_void_p(plan.handle),
+                                            xa.ctypes.data_as(ctypes.c_void_p), float(in_scale), flags,
+                                            float(arrival), ctypes.byref(t)))
+        return int(t.value)
+
+    def query(self, ticket: int) -> dict:
+        info = FrameInfo()
+        _check(self._lib.dmas_server_query(self._h, ticket, ctypes.byref(info)))
+        return info.as_dict()
+
+    def wait(self, ticket: int, timeout: float = 60.0) -> dict:
+        info = FrameInfo()
+        _check(self._lib.dmas_server_wait(self._h, ticket, float(timeout), ctypes.byref(info)))
+        return info.as_dict()
+
+    def fetch(self, ticket: int, shape) -> np.ndarray:
+        out = np.empty(shape, dtype=np.float32)
+        _check(self._lib.dmas_server_fetch(self._h, ticket, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def release(self, ticket: int) -> None:
+        _check(self._lib.dmas_server_release(self._h, ticket))
+
+    def completed(self, max_records: int = 4096) -> list:
+        buf = (FrameInfo * max_records)()
+        n = ctypes.c_int32()
+        _check(self._lib.dmas_server_completed(self._h, buf, max_records, ctypes.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def drain(self, timeout: float = 300.0) -> None:
+        _check(self._lib.dmas_server_drain(self._h, float(timeout)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.dmas_server_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}

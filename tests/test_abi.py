@@ -51,7 +51,10 @@ def _c_layout(struct, fields, tmp_path):
     return vals[0], vals[1:]
 
 
-@pytest.mark.parametrize("struct,mirror", [("dmas_plan_desc_t", dmas.PlanDesc), ("dmas_plan_info_t", dmas.PlanInfo)])
+@pytest.mark.parametrize("struct,mirror", [("dmas_plan_desc_t", dmas.PlanDesc), ("dmas_plan_info_t", dmas.PlanInfo),
+                                           ("dmas_server_desc_t", dmas.ServerDesc),
+                                           ("dmas_frame_info_t", dmas.FrameInfo),
+                                           ("dmas_server_stats_t", dmas.ServerStats)])
 def test_struct_layouts_match_header(lib, tmp_path, struct, mirror):
     """The ctypes mirrors have the C layout: same size and field offsets as the header."""
     fields = [name for name, _ in mirror._fields_]
