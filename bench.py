@@ -260,7 +260,10 @@ def bench_serving(args) -> list:
         picks = rng.integers(0, len(pool), size=n_frames)
         for mode, kw in modes:
             with Server(hbm_budget=64 << 30, staging=2 << 30, **kw) as srv:
-                # warm up every plan once (first launches of each kernel)
+                # warm up every kernel the trace can use: each plan alone, then all at once
+                for k in range(len(pool)):
+                    srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
+                    srv.drain(600)
                 for k in range(len(pool)):
                     srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
                 srv.drain(600)

@@ -114,7 +114,20 @@ struct Launch {
     std::vector<Frame *> frames;
     hipEvent_t done = nullptr;
     bool busy = false;
+    double t_launch = 0;      // issue time
+    double t_start = 0;       // when it had the device to itself (previous launch done, or issue)
+    double work = 0;          // modelled VALU work (lane-op slots)
+    int64_t workgroups = 0;
+    double tail_start = 0;    // predicted start of its last device round
 };
+
+// Modelled VALU issue slots of one frame (per-microphone root and power sums,
+// Newton-Girard, CF and envelope per pixel); used only to predict durations.
+double frame_work(const dmas_plan_s *p, bool env)
+{
+    const double per_mic = p->order == 1 ? 2.0 : p->order == 2 ? 7.0 : 8.0 + p->order;
+    return (double)p->D * p->T * (p->M * per_mic + 30.0 + (env ? p->fir_len : 0));
+}
 
 size_t elem_size(int dtype)
 {
@@ -147,6 +160,8 @@ struct dmas_server_s {
     size_t budget = 0, staging = 0;
     int nstreams = 2, max_batch = 64;
     int64_t batch_wg_cap = 0;   // workgroups per multi-frame launch (about two device rounds)
+    int64_t resident_wgs = 0;   // workgroups the device holds at once (typical occupancy)
+    double rate = 3.0e13;       // learned work rate (modelled slots per second)
     char *d_arena = nullptr;
     char *h_staging = nullptr;
     Arena arena, stage_arena;
@@ -238,6 +253,12 @@ struct dmas_server_s {
                 }
             }
             if (q != hipSuccess) worker_error = hipGetErrorString(q);
+            if (q == hipSuccess && t > l.t_start && l.work > 0) {
+                const double measured = l.work / (t - l.t_start);
+                rate = 0.8 * rate + 0.2 * measured;
+            }
+            for (auto &other : launches)
+                if (other.busy && &other != &l) other.t_start = std::max(other.t_start, t);
             l.frames.clear();
             l.busy = false;
             progress = true;
@@ -287,13 +308,19 @@ struct dmas_server_s {
     {
         bool progress = false;
         while (!admitted.empty()) {
+            // A new launch may overlap running ones only in their predicted last
+            // device round: overlapping their main body would only slow them down.
+            const double t_now = now_s();
             int s = -1;
-            for (int i = 0; i < nstreams; ++i)
-                if (!launches[i].busy) {
+            bool blocked = false;
+            for (int i = 0; i < nstreams; ++i) {
+                if (launches[i].busy) {
+                    if (t_now < launches[i].tail_start) blocked = true;
+                } else if (s < 0) {
                     s = i;
-                    break;
                 }
-            if (s < 0) break;
+            }
+            if (s < 0 || blocked) break;
             Launch &l = launches[s];
             hipStream_t st = streams[s];
             Frame *head = admitted.front();
@@ -361,6 +388,29 @@ struct dmas_server_s {
             }
             if (e == hipSuccess) e = hipEventRecord(l.done, st);
             const double t = now_s();
+            {
+                double work = 0;
+                int64_t wgs = 0;
+                for (Frame *f : group) {
+                    work += frame_work(f->plan, f->env);
+                    wgs += dmas::plan_workgroups(f->plan, f->env);
+                }
+                bool alone = true;
+                for (auto &other : launches)
+                    if (other.busy) alone = false;
+                const double dur = work / rate;
+                l.t_launch = t;
+                l.t_start = t;
+                if (!alone) {
+                    // starts on the leftover CUs of the running launches
+                    for (auto &other : launches)
+                        if (other.busy) l.t_start = std::max(l.t_start, other.t_start + other.work / rate);
+                }
+                l.work = work;
+                l.workgroups = wgs;
+                const double body = wgs > resident_wgs ? 1.0 - (double)resident_wgs / (double)wgs : 0.0;
+                l.tail_start = l.t_start + dur * body;
+            }
             ++n_launches;
             if (group.size() > 1) n_batched += (int64_t)group.size();
             for (Frame *f : group) {
@@ -441,7 +491,8 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
         hipDeviceProp_t prop;
         int cus = 256;
         if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) cus = prop.multiProcessorCount;
-        s->batch_wg_cap = (int64_t)2 * 3 * cus;
+        s->resident_wgs = (int64_t)3 * cus;
+        s->batch_wg_cap = 2 * s->resident_wgs;
     }
     auto fail_all = [&](hipError_t e, const char *what) {
         dmas_server_destroy(s);
