@@ -80,6 +80,7 @@ typedef enum { DMAS_DELAY_NEAREST = 0, DMAS_DELAY_LINEAR = 1 } dmas_delay_mode_t
 /* Largest supported order n and envelope length L. */
 #define DMAS_MAX_ORDER 8
 #define DMAS_MAX_FIR_LEN 255
+#define DMAS_MAX_MF_LEN 8192
 
 /*
  * Plan description. Initialise with dmas_plan_desc_init() and then set the
@@ -105,6 +106,12 @@ typedef struct {
     int32_t ng_fp64;       /* 0/1: evaluate eqs. (8)-(12) in FP64 instead of FP32 */
     int32_t compensated;   /* 0/1: compensated (Kahan) FP32 accumulation of the power sums */
     int32_t delay_mode;    /* dmas_delay_mode_t */
+    int32_t env_decimation; /* envelope output keeps every k-th sample (k >= 1; 0 selects 1):
+                               dmas_envelope writes D x ceil(T/k), element [p*ceil(T/k) + j]
+                               = env[p][j*k] */
+    const float *mf_pulse; /* host, mf_len samples of the emitted pulse for
+                              dmas_matched_filter; NULL: no matched filter */
+    int32_t mf_len;        /* 0..DMAS_MAX_MF_LEN */
 } dmas_plan_desc_t;
 
 /* Read-only facts about a created plan (tiling chosen for the device). */
@@ -142,9 +149,16 @@ dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y,
                             float in_scale, void *stream);
 
 /* DMAS-n (+CF) image followed by envelope detection in the same kernel:
- * writes d_env (D x T FP32, device). */
+ * writes d_env (D x ceil(T/k) FP32, device; k = env_decimation). */
 dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env,
                             float in_scale, void *stream);
+
+/* Matched filter (pulse compression, the pipeline step before the
+ * beamformer, Section II): d_x[i*T + t] = sum_{k < mf_len} d_raw[i*T + t + k]
+ * * pulse[k], raw = 0 beyond the record. d_raw and d_x are M x T FP32 device
+ * arrays (the plan must have in_dtype F32 and a pulse); d_x is then the input
+ * of dmas_beamform / dmas_envelope. FP32 accumulation in index order. */
+dmas_status_t dmas_matched_filter(dmas_plan_t plan, const float *d_raw, float *d_x, void *stream);
 
 /* The steering delays the beamformer uses, eq. (1), computed by the same
  * device code: d_whole (D x M int32, device) receives floor(fs*tau + 1/2) in

@@ -48,8 +48,9 @@ def _load():
                                      _i64p, _dp, _dp]
     lib.oracle_envelope.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp]
     lib.oracle_lowpass_taps.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp]
+    lib.oracle_matched_filter.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp]
     for f in (lib.oracle_delays, lib.oracle_delays_frac, lib.oracle_dmas_rows,
-              lib.oracle_envelope, lib.oracle_lowpass_taps):
+              lib.oracle_envelope, lib.oracle_lowpass_taps, lib.oracle_matched_filter):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -151,3 +152,17 @@ def frame_rows(frame, rows=None, diag: bool = False, interp: bool = False, x=Non
     return dmas_rows(frame.x if x is None else x, frame.mic_pos, frame.dirs, frame.fs, frame.c,
                      frame.order, frame.use_cf, frame.nearfield, rows=rows, diag=diag,
                      interp=interp, cf_eps=cf_eps)
+
+
+def matched_filter(raw, pulse) -> np.ndarray:
+    """Pulse compression (Section II, pipeline step 1): r[t] = sum_k m[t + k] p[k], m = 0 beyond the record."""
+    rv = _f64(raw)
+    if rv.ndim == 1:
+        rv = rv[None, :]
+    pv = _f64(pulse)
+    M, T = rv.shape
+    out = np.zeros_like(rv)
+    rc = _load().oracle_matched_filter(M, T, _ptr(rv), int(pv.size), _ptr(pv), _ptr(out))
+    if rc:
+        raise ValueError("oracle_matched_filter: invalid arguments")
+    return out

@@ -26,6 +26,9 @@
  *   5. Envelope (Section II, step 3 of the pipeline): |y| filtered by a
  *      zero-phase FIR, env[t] = sum_k h[k] |y[t + (L-1)/2 - k]|, y = 0 outside
  *      the record.
+ * Upstream of the beamformer (pipeline step 1 of Section II), the matched
+ * filter correlates each raw channel with the emitted pulse:
+ * r[t] = sum_k m[t + k] p[k], m = 0 beyond the record.
  * Diagnostics (optional): per pixel E_n, CF, the complete homogeneous
  * symmetric polynomial h_n(|s|) (the error-amplification scale of any
  * power-sum evaluation of E_n), sum x, sum x^2 and sum |x|.
@@ -281,5 +284,24 @@ int oracle_lowpass_taps(int L, double fc, double fs, double *taps)
     }
     for (int k = 0; k < L; ++k)
         taps[k] /= sum;
+    return 0;
+}
+
+/* Matched filter (pulse compression): out[i*T + t] = sum_{k<P} raw[i*T + t + k] * pulse[k],
+ * with raw = 0 beyond the record. */
+int oracle_matched_filter(int M, int T, const double *raw, int P, const double *pulse, double *out)
+{
+    if (M < 1 || T < 1 || P < 1 || !raw || !pulse || !out)
+        return 1;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < M; ++i) {
+        const double *ch = raw + (int64_t)i * T;
+        for (int64_t t = 0; t < T; ++t) {
+            double acc = 0.0;
+            for (int k = 0; k < P && t + k < T; ++k)
+                acc += ch[t + k] * pulse[k];
+            out[(int64_t)i * T + t] = acc;
+        }
+    }
     return 0;
 }

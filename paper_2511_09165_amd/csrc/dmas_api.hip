@@ -139,6 +139,7 @@ void plan_free(dmas_plan_s *p)
     hipFree(p->d_dirs);
     hipFree(p->d_tiles);
     hipFree(p->d_taps);
+    hipFree(p->d_pulse);
     if (switched) hipSetDevice(cur);
     delete p;
 }
@@ -361,6 +362,7 @@ dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *d)
     d->fir_fc = 5000.0;
     d->in_dtype = DMAS_F32;
     d->delay_mode = DMAS_DELAY_NEAREST;
+    d->env_decimation = 1;
     return DMAS_OK;
 }
 
@@ -413,6 +415,14 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         return fail(DMAS_ERR_UNSUPPORTED, "linear delays are built with CF only");
     if (d->delay_mode == DMAS_DELAY_LINEAR && d->compensated)
         return fail(DMAS_ERR_UNSUPPORTED, "linear delays with compensated sums are not built");
+    const int decim = d->env_decimation == 0 ? 1 : d->env_decimation;
+    if (decim < 1 || decim > T) return fail(DMAS_ERR_INVALID_ARG, "env_decimation %d must lie in 1..T", decim);
+    if (d->mf_len < 0 || d->mf_len > DMAS_MAX_MF_LEN || (d->mf_pulse && d->mf_len < 1) || (!d->mf_pulse && d->mf_len))
+        return fail(DMAS_ERR_INVALID_ARG, "mf_len must be 1..%d with mf_pulse, 0 without", DMAS_MAX_MF_LEN);
+    if (d->mf_pulse) {
+        for (int k = 0; k < d->mf_len; ++k)
+            if (!std::isfinite(d->mf_pulse[k])) return fail(DMAS_ERR_INVALID_ARG, "mf_pulse contains NaN or Inf");
+    }
     if (d->fir_taps) {
         for (int k = 0; k < L; ++k)
             if (!std::isfinite(d->fir_taps[k])) return fail(DMAS_ERR_INVALID_ARG, "fir_taps contain NaN or Inf");
@@ -442,6 +452,8 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->c = c;
     p->cf_eps = (float)eps;
     p->fir_len = L;
+    p->env_decim = decim;
+    p->mf_len = d->mf_pulse ? d->mf_len : 0;
 
     // ---- tiles of nearby directions (Morton order, greedy within a delay budget) ----
     constexpr int W = dmas::kDirsPerTile;
@@ -468,7 +480,8 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     if ((st = dev_copy((void **)&p->d_mic, d->mic_pos, sizeof(double) * 3 * M, "mic_pos")) != DMAS_OK ||
         (st = dev_copy((void **)&p->d_dirs, d->dirs, sizeof(double) * 3 * (size_t)D, "dirs")) != DMAS_OK ||
         (st = dev_copy((void **)&p->d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(), "tiles")) != DMAS_OK ||
-        (st = dev_copy((void **)&p->d_taps, taps.data(), sizeof(float) * L, "taps")) != DMAS_OK) {
+        (st = dev_copy((void **)&p->d_taps, taps.data(), sizeof(float) * L, "taps")) != DMAS_OK ||
+        (p->mf_len && (st = dev_copy((void **)&p->d_pulse, d->mf_pulse, sizeof(float) * p->mf_len, "pulse")) != DMAS_OK)) {
         plan_free(p);
         return st;
     }
@@ -596,6 +609,22 @@ dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y, float
 dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env, float in_scale, void *stream)
 {
     return run(plan, d_x, d_env, in_scale, stream, true);
+}
+
+dmas_status_t dmas_matched_filter(dmas_plan_t p, const float *d_raw, float *d_x, void *stream)
+{
+    if (!p || !d_raw || !d_x) return fail(DMAS_ERR_INVALID_ARG, "plan or device pointer is NULL");
+    if (!p->mf_len) return fail(DMAS_ERR_INVALID_ARG, "the plan has no matched-filter pulse");
+    if (p->dtype != DMAS_F32) return fail(DMAS_ERR_UNSUPPORTED, "the matched filter writes FP32 channels");
+    if (p->M > 65535) return fail(DMAS_ERR_UNSUPPORTED, "matched filter supports up to 65535 channels");
+    if (d_raw == d_x) return fail(DMAS_ERR_INVALID_ARG, "the matched filter cannot run in place");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(DMAS_ERR_INVALID_ARG, "plan belongs to device %d but device %d is current", p->device, cur);
+    hipError_t e = dmas::launch_matched_filter(d_raw, p->d_pulse, p->M, p->T, p->mf_len, d_x,
+                                               static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "matched filter launch");
+    return DMAS_OK;
 }
 
 dmas_status_t dmas_steering_delays(dmas_plan_t p, int32_t *d_whole, float *d_frac, void *stream)

@@ -33,6 +33,8 @@ struct KernelParams {
     double fs, c;
     float cf_eps;
     float in_scale;
+    int32_t env_decim;        // envelope keeps every env_decim-th sample
+    int32_t out_T;            // output row length: T, or ceil(T / env_decim) for the envelope
 };
 
 // A batch of frames for the multi-frame kernel (device pointers).
@@ -71,6 +73,10 @@ hipError_t launch_batch_order5(const BatchParams &, bool, bool, bool, unsigned, 
 hipError_t launch_batch_order6(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
 hipError_t launch_batch_order7(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
 hipError_t launch_batch_order8(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+
+// Matched filter: out[i*T + t] = sum_{k<P} raw[i*T + t + k] * pulse[k].
+hipError_t launch_matched_filter(const float *raw, const float *pulse, int M, int T, int P, float *out,
+                                 hipStream_t stream);
 
 hipError_t launch_order1(const KernelParams *, const LaunchShape &, hipStream_t, int *);
 hipError_t launch_order2(const KernelParams *, const LaunchShape &, hipStream_t, int *);

@@ -391,7 +391,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 
         if (!active) continue;
         // ---- epilogue: Newton-Girard, CF, store or envelope ----
-        const size_t orow = (size_t)dir * (size_t)p.T;
+        const size_t orow = (size_t)dir * (size_t)p.out_T;
         if constexpr (!ENV) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -409,19 +409,38 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             // env[t] for t = tc - H + o, o in [0, C): sum_k h[k] |y[t + H - k]|
-            float e[K];
+            if (p.env_decim == 1) {
+                float e[K];
 #pragma unroll
-            for (int j = 0; j < K; ++j) e[j] = 0.0f;
-            for (int k = 0; k < p.fir_len; ++k) {
-                const float h = taps[k];
-                const float *src = ring + 2 * H - k + lane;
+                for (int j = 0; j < K; ++j) e[j] = 0.0f;
+                for (int k = 0; k < p.fir_len; ++k) {
+                    const float h = taps[k];
+                    const float *src = ring + 2 * H - k + lane;
 #pragma unroll
-                for (int j = 0; j < K; ++j) e[j] = __builtin_fmaf(h, src[kWaveSize * j], e[j]);
-            }
+                    for (int j = 0; j < K; ++j) e[j] = __builtin_fmaf(h, src[kWaveSize * j], e[j]);
+                }
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const int t = tc - H + lane + kWaveSize * j;
-                if (t >= g0 && t < g1) __builtin_nontemporal_store(e[j], p.out + orow + t);
+                for (int j = 0; j < K; ++j) {
+                    const int t = tc - H + lane + kWaveSize * j;
+                    if (t >= g0 && t < g1) __builtin_nontemporal_store(e[j], p.out + orow + t);
+                }
+            } else {
+                // Decimated envelope: only the outputs at t = j * env_decim, each
+                // owned by the segment that contains t.
+                const int dec = p.env_decim;
+                const int t_lo = tc - H;
+                const int lo = max(t_lo, g0);
+                const int hi = min(t_lo + C, g1);
+                if (hi > lo) {
+                    const int j0 = (lo + dec - 1) / dec;   // lo >= 0
+                    const int j1 = (hi + dec - 1) / dec;
+                    for (int jo = j0 + lane; jo < j1; jo += kWaveSize) {
+                        const float *src = ring + 2 * H + (jo * dec - t_lo);
+                        float e = 0.0f;
+                        for (int k = 0; k < p.fir_len; ++k) e = __builtin_fmaf(taps[k], src[-k], e);
+                        __builtin_nontemporal_store(e, p.out + orow + jo);
+                    }
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();

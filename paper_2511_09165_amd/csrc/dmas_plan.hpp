@@ -30,6 +30,9 @@ struct dmas_plan_s {
     double *d_dirs = nullptr;
     int32_t *d_tiles = nullptr;
     float *d_taps = nullptr;
+    int env_decim = 1;
+    int mf_len = 0;
+    float *d_pulse = nullptr;
 };
 
 namespace dmas {
@@ -60,6 +63,8 @@ inline KernelParams make_params(const dmas_plan_s *plan, const void *d_x, float 
     kp.c = plan->c;
     kp.cf_eps = plan->cf_eps;
     kp.in_scale = in_scale;
+    kp.env_decim = env ? plan->env_decim : 1;
+    kp.out_T = env ? (plan->T + plan->env_decim - 1) / plan->env_decim : plan->T;
     return kp;
 }
 

@@ -162,6 +162,7 @@ struct dmas_server_s {
     int64_t batch_wg_cap = 0;   // workgroups per multi-frame launch (about two device rounds)
     int64_t resident_wgs = 0;   // workgroups the device holds at once (typical occupancy)
     double rate = 3.0e13;       // learned work rate (modelled slots per second)
+    double rate_cap = 3.6e13;   // about 92% of the VALU issue peak of the device
     char *d_arena = nullptr;
     char *h_staging = nullptr;
     Arena arena, stage_arena;
@@ -208,7 +209,7 @@ struct dmas_server_s {
         info->t_launch = f->t_launch;
         info->t_done = f->t_done;
         info->d_out = (f->on_device && f->state == kDone) ? reinterpret_cast<float *>(d_arena + f->out_off) : nullptr;
-        info->pixels = (int64_t)f->plan->D * f->plan->T;
+        info->pixels = (int64_t)f->plan->D * f->plan->T;   // beamformed pixels (before decimation)
     }
 
     void free_device(Frame *f)
@@ -254,7 +255,8 @@ struct dmas_server_s {
             }
             if (q != hipSuccess) worker_error = hipGetErrorString(q);
             if (q == hipSuccess && t > l.t_start && l.work > 0) {
-                const double measured = l.work / (t - l.t_start);
+                // the modelled work cannot run faster than the device's issue rate
+                const double measured = std::min(std::max(l.work / (t - l.t_start), 0.25 * rate_cap), rate_cap);
                 rate = 0.8 * rate + 0.2 * measured;
             }
             for (auto &other : launches)
@@ -492,6 +494,10 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
         int cus = 256;
         if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) cus = prop.multiProcessorCount;
         s->resident_wgs = (int64_t)3 * cus;
+        // 4 SIMDs x 16 lanes per CU at the peak clock (kHz in clockRate)
+        const double clk = prop.clockRate > 0 ? prop.clockRate * 1e3 : 2.4e9;
+        s->rate_cap = 0.92 * cus * 64.0 * clk;
+        s->rate = std::min(s->rate, s->rate_cap);
         s->batch_wg_cap = 2 * s->resident_wgs;
     }
     auto fail_all = [&](hipError_t e, const char *what) {
@@ -540,7 +546,8 @@ dmas_status_t dmas_server_submit(dmas_server_t s, dmas_plan_t plan, const void *
     f->env = (flags & DMAS_SUBMIT_ENVELOPE) != 0;
     f->auto_release = (flags & DMAS_SUBMIT_AUTO_RELEASE) != 0;
     f->in_bytes = (size_t)plan->M * plan->T * elem_size(plan->dtype);
-    f->out_bytes = (size_t)plan->D * plan->T * sizeof(float);
+    const size_t out_T = f->env ? (size_t)(plan->T + plan->env_decim - 1) / plan->env_decim : (size_t)plan->T;
+    f->out_bytes = (size_t)plan->D * out_T * sizeof(float);
     if (align_up(f->in_bytes) + align_up(f->out_bytes) > s->budget) {
         delete f;
         return srv_fail(DMAS_ERR_INVALID_ARG, "frame input + output exceed the server's HBM budget");

@@ -24,7 +24,7 @@ SUBMIT_AUTO_RELEASE = 2
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTED = ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
             "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass",
-            "dmas_last_error", "dmas_version",
+            "dmas_matched_filter", "dmas_last_error", "dmas_version",
             "dmas_server_clock", "dmas_server_create", "dmas_server_submit", "dmas_server_query",
             "dmas_server_wait", "dmas_server_release", "dmas_server_fetch", "dmas_server_completed",
             "dmas_server_drain", "dmas_server_stats", "dmas_server_destroy")
@@ -44,7 +44,8 @@ class PlanDesc(ctypes.Structure):
         ("fs", ctypes.c_double), ("c", ctypes.c_double), ("cf_eps", ctypes.c_double),
         ("fir_taps", ctypes.POINTER(ctypes.c_float)), ("fir_len", ctypes.c_int32), ("fir_fc", ctypes.c_double),
         ("in_dtype", ctypes.c_int32), ("ng_fp64", ctypes.c_int32), ("compensated", ctypes.c_int32),
-        ("delay_mode", ctypes.c_int32),
+        ("delay_mode", ctypes.c_int32), ("env_decimation", ctypes.c_int32),
+        ("mf_pulse", ctypes.POINTER(ctypes.c_float)), ("mf_len", ctypes.c_int32),
     ]
 
 
@@ -96,6 +97,8 @@ def load_library(path: Optional[str] = None):
     lib.dmas_beamform.argtypes = [vp, vp, vp, ctypes.c_float, vp]
     lib.dmas_envelope.argtypes = [vp, vp, vp, ctypes.c_float, vp]
     lib.dmas_steering_delays.argtypes = [vp, vp, vp, vp]
+    lib.dmas_matched_filter.argtypes = [vp, vp, vp, vp]
+    lib.dmas_matched_filter.restype = st
     lib.dmas_design_lowpass.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_float)]
     for name in ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
@@ -160,7 +163,8 @@ class Plan:
     def __init__(self, mic_pos, dirs, num_samples: int, order: int, fs: float, c: float = 343.0,
                  use_cf: bool = True, nearfield: bool = False, fir_taps=None, fir_len: int = 63,
                  fir_fc: float = 5000.0, in_dtype: str = "f32", ng_fp64: bool = False,
-                 compensated: bool = False, linear: bool = False, cf_eps: float = 1e-20):
+                 compensated: bool = False, linear: bool = False, cf_eps: float = 1e-20,
+                 env_decimation: int = 1, mf_pulse=None):
         lib = load_library()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -187,7 +191,15 @@ class Plan:
         d.fir_fc = float(fir_fc)
         d.in_dtype = DTYPES[in_dtype]
         d.ng_fp64, d.compensated, d.delay_mode = int(bool(ng_fp64)), int(bool(compensated)), int(bool(linear))
+        d.env_decimation = int(env_decimation)
+        pulse = None
+        if mf_pulse is not None:
+            pulse = np.ascontiguousarray(np.asarray(mf_pulse, dtype=np.float32))
+            d.mf_pulse = pulse.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            d.mf_len = pulse.size
         _check(lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(self._handle)))
+        self.env_decimation = max(1, int(env_decimation))
+        self.env_samples = -(-int(num_samples) // self.env_decimation)
         self.num_mics, self.num_samples, self.num_dirs = d.num_mics, d.num_samples, d.num_dirs
         self.order, self.in_dtype = int(order), in_dtype
         self.use_cf, self.nearfield, self.linear = bool(use_cf), bool(nearfield), bool(linear)
@@ -228,13 +240,14 @@ class Plan:
             raise ValueError(f"x must be a contiguous {want} device tensor of shape "
                              f"({self.num_mics}, {self.num_samples}); got {x.dtype} {tuple(x.shape)}")
 
-    def _out(self, x, out):
+    def _out(self, x, out, samples=None):
         import torch
+        shape = (self.num_dirs, self.num_samples if samples is None else samples)
         if out is None:
-            return torch.empty((self.num_dirs, self.num_samples), dtype=torch.float32, device=x.device)
-        if out.dtype != torch.float32 or tuple(out.shape) != (self.num_dirs, self.num_samples) \
-                or not out.is_contiguous() or out.device != x.device:
-            raise ValueError("out must be a contiguous float32 (D, T) tensor on the input's device")
+            return torch.empty(shape, dtype=torch.float32, device=x.device)
+        if out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous() \
+                or out.device != x.device:
+            raise ValueError(f"out must be a contiguous float32 {shape} tensor on the input's device")
         return out
 
     def beamform(self, x, out=None, in_scale: float = 1.0, stream=None):
@@ -247,12 +260,25 @@ class Plan:
         return out
 
     def envelope(self, x, out=None, in_scale: float = 1.0, stream=None):
-        """DMAS-n (+CF) image followed by the envelope filter, (D, T) float32."""
+        """DMAS-n (+CF) image followed by the envelope filter, (D, ceil(T / env_decimation)) float32."""
         self._check_input(x)
-        out = self._out(x, out)
+        out = self._out(x, out, self.env_samples)
         _check(self._lib.dmas_envelope(self._handle, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), float(in_scale),
                                        ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def matched_filter(self, raw, out=None, stream=None):
+        """Pulse compression of raw (M, T) float32 device channels with the plan's pulse."""
+        import torch
+        if not raw.is_cuda or raw.dtype != torch.float32 or tuple(raw.shape) != (self.num_mics, self.num_samples) \
+                or not raw.is_contiguous():
+            raise ValueError("raw must be a contiguous float32 (M, T) device tensor")
+        if out is None:
+            out = torch.empty_like(raw)
+        _check(self._lib.dmas_matched_filter(self._handle, ctypes.c_void_p(raw.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(_stream_handle(stream))))
         return out
 
     def steering_delays(self, stream=None):

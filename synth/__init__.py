@@ -250,7 +250,8 @@ def config1(seed_salt: int = 0, order: int = 2) -> Frame:
 def echo_frame(rng: np.random.Generator, mics: np.ndarray, dirs: np.ndarray, T: int,
                n_reflectors: int, order: int, fs: float = 450e3, c: float = SPEED_OF_SOUND,
                az_range=(-90.0, 90.0), el_range=(-45.0, 45.0), r_range=(0.3, 5.0),
-               chirp=(25e3, 75e3, 1e-3), snr_db: float = 20.0, name: str = "echo") -> Frame:
+               chirp=(25e3, 75e3, 1e-3), snr_db: float = 20.0, name: str = "echo",
+               apply_matched_filter: bool = True) -> Frame:
     """Pulse-echo frame: a chirp from an emitter at the origin, point reflectors, noise, matched filter.
 
     Reflector p at range r has amplitude 1/r^2; its echo reaches microphone i after
@@ -276,9 +277,9 @@ def echo_frame(rng: np.random.Generator, mics: np.ndarray, dirs: np.ndarray, T: 
     strongest = max(d["amp"] for d in refl) if refl else 1.0
     sigma = strongest * np.sqrt(np.mean(pulse ** 2)) / 10 ** (snr_db / 20.0)
     raw += rng.normal(0.0, sigma, size=raw.shape)
-    x = matched_filter(raw, pulse)
+    x = matched_filter(raw, pulse) if apply_matched_filter else raw
     return Frame(name, x, mics, dirs, fs, c, order, True, False,
-                 truth=dict(reflectors=refl, pulse_len=pulse.size, sigma=sigma))
+                 truth=dict(reflectors=refl, pulse_len=pulse.size, sigma=sigma, pulse=pulse))
 
 
 def config2(seed_salt: int = 0, order: int = 5, num_samples: int = 16384) -> Frame:

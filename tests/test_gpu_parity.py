@@ -276,3 +276,66 @@ def test_bad_inputs_rejected():
             plan.beamform(torch.zeros((4, 49), dtype=torch.float32, device="cuda"))
         with pytest.raises(DmasError):
             plan.beamform(torch.zeros((4, 50), dtype=torch.float32, device="cuda"), in_scale=0.0)
+
+
+# ---------------------------------------------------------------------------
+# Steps either side of the beamformer: matched filter and envelope decimation
+# ---------------------------------------------------------------------------
+
+def _raw_frame(M=16, D=60, T=3000, n=3, seed=90):
+    rng = np.random.default_rng(seed)
+    mics = synth.disc_array(rng, M, 0.1)
+    dirs = synth.az_el_grid(np.linspace(-60, 60, D // 3), [-10.0, 0.0, 10.0])
+    return synth.echo_frame(rng, mics, dirs, T, 6, n, r_range=(0.3, 1.2), apply_matched_filter=False)
+
+
+def test_matched_filter_parity():
+    """GPU pulse compression vs the oracle: per element |d| <= 2 (P + 2) u sum_k |m[t+k] p[k]|."""
+    f = _raw_frame()
+    pulse = f.truth["pulse"].astype(np.float32)
+    raw32 = f.x_f32()
+    with _plan(f, mf_pulse=pulse) as plan:
+        got = plan.matched_filter(torch.from_numpy(raw32).cuda()).cpu().numpy().astype(np.float64)
+    ref = oracle.matched_filter(raw32.astype(np.float64), pulse.astype(np.float64))
+    scale = oracle.matched_filter(np.abs(raw32.astype(np.float64)), np.abs(pulse.astype(np.float64)))
+    bound = 2 * (pulse.size + 2) * 2.0 ** -24 * scale + 1e-30
+    assert np.all(np.abs(got - ref) <= bound), float((np.abs(got - ref) / bound).max())
+    check_t1(got, ref, tol=1e-5)
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_raw_to_envelope_pipeline(n):
+    """raw -> matched filter -> DMAS-n+CF -> envelope on the GPU vs the same chain in the oracle."""
+    f = _raw_frame(n=n, seed=91 + n)
+    pulse = f.truth["pulse"].astype(np.float32)
+    raw32 = f.x_f32()
+    taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32)
+    with _plan(f, mf_pulse=pulse, fir_taps=taps) as plan:
+        x = plan.matched_filter(torch.from_numpy(raw32).cuda())
+        env = plan.envelope(x).cpu().numpy().astype(np.float64)
+    x_ref = oracle.matched_filter(raw32.astype(np.float64), pulse.astype(np.float64))
+    env_ref = oracle.envelope(oracle.frame_rows(f, x=x_ref), taps.astype(np.float64))
+    check_t1(env, env_ref)
+
+
+@pytest.mark.parametrize("k", [2, 7, 16])
+def test_envelope_decimation(k):
+    """Every k-th envelope sample: bitwise equal to the full-rate envelope, and to the oracle within T1."""
+    f = synth.random_frame(np.random.default_rng(95 + k), 24, 30, 5000, 5)
+    taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32)
+    full = _run(f, f.x_f32(), env=True, taps=taps)
+    dec = _run(f, f.x_f32(), env=True, taps=taps, env_decimation=k)
+    assert dec.shape == (f.num_dirs, -(-f.num_samples // k))
+    assert np.array_equal(dec, full[:, ::k])
+    env_ref = oracle.envelope(oracle.frame_rows(f, x=f.x_f32().astype(np.float64)), taps.astype(np.float64))
+    check_t1(dec, env_ref[:, ::k])
+
+
+def test_plan_rejects_bad_pipeline_options():
+    from paper_2511_09165_amd import DmasError
+    f = synth.random_frame(np.random.default_rng(96), 8, 5, 100, 2)
+    with pytest.raises(DmasError):
+        _plan(f, env_decimation=101)
+    with _plan(f) as plan:
+        with pytest.raises(DmasError):
+            plan.matched_filter(torch.zeros((8, 100), dtype=torch.float32, device="cuda"))

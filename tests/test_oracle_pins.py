@@ -350,3 +350,20 @@ def test_invalid_arguments_rejected():
         oracle.dmas_rows(np.ones((3, 5)), np.zeros((3, 3)), np.array([[0, 0, 1.0]]), 450e3, 343.0, 4)
     with pytest.raises(ValueError):
         oracle.envelope(np.ones((1, 5)), np.ones(4))
+
+
+def test_matched_filter_matches_numpy_and_fft():
+    """Pulse compression equals numpy's 'valid' correlation of the zero-padded channel and an FFT correlation."""
+    rng = np.random.default_rng(41)
+    raw = rng.standard_normal((3, 500))
+    pulse = synth.linear_chirp(450e3, 25e3, 75e3, 1e-4)
+    out = oracle.matched_filter(raw, pulse)
+    for i in range(3):
+        padded = np.concatenate([raw[i], np.zeros(pulse.size - 1)])
+        np.testing.assert_allclose(out[i], np.correlate(padded, pulse, mode="valid"), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out, synth.matched_filter(raw, pulse), rtol=1e-9, atol=1e-9)
+    # an echo of the pulse at sample 100 peaks at 100 with the pulse energy
+    echo = np.zeros((1, 400))
+    echo[0, 100:100 + pulse.size] = pulse
+    r = oracle.matched_filter(echo, pulse)[0]
+    assert int(np.argmax(r)) == 100 and r[100] == pytest.approx(np.sum(pulse ** 2), rel=1e-12)

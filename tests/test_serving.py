@@ -49,9 +49,9 @@ def _run_server(frames, plans, **server_kw):
     outs, infos = [], []
     with Server(**server_kw) as srv:
         tickets = [srv.submit(p, f.x_f32(), envelope=f.env) for f, p in zip(frames, plans)]
-        for f, t in zip(frames, tickets):
+        for f, p, t in zip(frames, plans, tickets):
             infos.append(srv.wait(t, timeout=120))
-            outs.append(srv.fetch(t, (f.num_dirs, f.num_samples)))
+            outs.append(srv.fetch(t, (f.num_dirs, p.env_samples if f.env else f.num_samples)))
             srv.release(t)
         stats = srv.stats()
     return outs, infos, stats
@@ -60,7 +60,7 @@ def _run_server(frames, plans, **server_kw):
 def test_batched_equals_alone_bitwise():
     from paper_2511_09165_amd import plan_for_frame
     frames = _mix(1, 12)
-    plans = [plan_for_frame(f) for f in frames]
+    plans = [plan_for_frame(f, env_decimation=(4 if k % 5 == 2 else 1)) for k, f in enumerate(frames)]
     alone = [_standalone(p, f.x_f32(), f.env) for f, p in zip(frames, plans)]
     _say("serving: 12 frames, batching server")
     outs, infos, stats = _run_server(frames, plans, hbm_budget=4 << 30, num_streams=2, max_batch=64)
