@@ -492,10 +492,13 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
     {
         hipDeviceProp_t prop;
         int cus = 256;
-        if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) cus = prop.multiProcessorCount;
+        double clk = 2.4e9;   // peak clock; clockRate is in kHz
+        if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) {
+            cus = prop.multiProcessorCount;
+            if (prop.clockRate > 0) clk = prop.clockRate * 1e3;
+        }
         s->resident_wgs = (int64_t)3 * cus;
-        // 4 SIMDs x 16 lanes per CU at the peak clock (kHz in clockRate)
-        const double clk = prop.clockRate > 0 ? prop.clockRate * 1e3 : 2.4e9;
+        // 4 SIMDs x 16 lanes per CU issue one lane-instruction each per clock
         s->rate_cap = 0.92 * cus * 64.0 * clk;
         s->rate = std::min(s->rate, s->rate_cap);
         s->batch_wg_cap = 2 * s->resident_wgs;
