@@ -287,6 +287,12 @@ def bench_serving(args) -> list:
                 recs = srv.completed(n_frames + 10)
                 st = srv.stats()
             lat = np.array([r["t_done"] - r["t_arrival"] for r in recs]) * 1e3
+            slow = sorted(recs, key=lambda r: r["t_done"] - r["t_arrival"])[-3:]
+            slowest = [{"ms": round((r["t_done"] - r["t_arrival"]) * 1e3, 2),
+                        "queued_ms": round((r["t_admit"] - r["t_arrival"]) * 1e3, 2),
+                        "wait_launch_ms": round((r["t_launch"] - r["t_admit"]) * 1e3, 2),
+                        "run_ms": round((r["t_done"] - r["t_launch"]) * 1e3, 2),
+                        "frames_in_launch": r["batch_frames"], "pixels": r["pixels"]} for r in slow]
             done = np.array([r["t_done"] for r in recs])
             total_pix = float(sum(pix[k] for k in picks))
             span = float(done.max() - arrivals[0])
@@ -296,7 +302,7 @@ def bench_serving(args) -> list:
                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                         "max_ms": float(lat.max()), "launches": st["launches"] - launches0,
                         "mean_frames_per_launch": len(recs) / max(1, st["launches"] - launches0),
-                        "hbm_peak_gb": st["hbm_peak"] / 1e9, "busy_retries": busy_retries})
+                        "hbm_peak_gb": st["hbm_peak"] / 1e9, "busy_retries": busy_retries, "slowest": slowest})
             print(json.dumps(out[-1]), flush=True)
     for p in plans:
         p.close()

@@ -409,6 +409,20 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
                 return fail(DMAS_ERR_INVALID_ARG, "far-field direction %d is not a unit vector (|u| = %.9g)", p, nrm);
         }
     }
+    {
+        // Steering delays are whole samples in 32-bit integers: keep |fs*tau| far from overflow.
+        double rmax = 0, vmax = 0;
+        for (int i = 0; i < M; ++i)
+            rmax = std::max(rmax, std::sqrt(d->mic_pos[3 * i] * d->mic_pos[3 * i] + d->mic_pos[3 * i + 1] * d->mic_pos[3 * i + 1] +
+                                            d->mic_pos[3 * i + 2] * d->mic_pos[3 * i + 2]));
+        if (d->geometry == DMAS_NEARFIELD)
+            for (int q = 0; q < D; ++q)
+                vmax = std::max(vmax, std::sqrt(d->dirs[3 * q] * d->dirs[3 * q] + d->dirs[3 * q + 1] * d->dirs[3 * q + 1] +
+                                                d->dirs[3 * q + 2] * d->dirs[3 * q + 2]));
+        const double span = d->fs * (d->geometry == DMAS_NEARFIELD ? 2.0 * (rmax + vmax) : rmax) / c;
+        if (!(span < 1.0e8))
+            return fail(DMAS_ERR_INVALID_ARG, "geometry spans %.3g samples of delay; at most 1e8 is supported", span);
+    }
     if (d->compensated && (d->geometry != DMAS_FARFIELD || !d->use_cf))
         return fail(DMAS_ERR_UNSUPPORTED, "compensated accumulation is built for far field with CF only");
     if (d->delay_mode == DMAS_DELAY_LINEAR && !d->use_cf)

@@ -34,6 +34,8 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include <atomic>
+
 #include "dmas_internal.hpp"
 
 namespace dmas {
@@ -516,6 +518,27 @@ dmas_batch_kernel(const BatchParams bp)
     dmas_body<N, CF, ENV, NEAR, false, false>(p, local % p.num_tiles, local / p.num_tiles, smem);
 }
 
+// Dynamic LDS above 64 KiB must be allowed per kernel; the allowed size only
+// grows. One counter per kernel instantiation, safe to share between host
+// threads (a lost race only repeats the call).
+template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
+std::atomic<size_t> &lds_limit_slot()
+{
+    static std::atomic<size_t> allowed{64 * 1024};
+    return allowed;
+}
+
+inline hipError_t raise_lds_limit(const void *fn, size_t lds, std::atomic<size_t> &allowed)
+{
+    if (lds <= allowed.load(std::memory_order_relaxed)) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    size_t cur = allowed.load(std::memory_order_relaxed);
+    while (cur < lds && !allowed.compare_exchange_weak(cur, lds, std::memory_order_relaxed)) {
+    }
+    return hipSuccess;
+}
+
 // Host-side launcher for one order: picks the instantiation for the flags.
 // Instantiated: every (CF, envelope, geometry) with nearest delays; linear
 // delays with CF; compensated sums for the far field with CF.
@@ -523,14 +546,8 @@ template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
 hipError_t launch_one(const KernelParams &p, const LaunchShape &s, hipStream_t stream)
 {
     auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, COMP>;
-    static size_t lds_set = 64 * 1024;   // raised on demand; the limit only grows
-    if (s.lds_bytes > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)s.lds_bytes);
-        if (e != hipSuccess) return e;
-        lds_set = s.lds_bytes;
-    }
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), s.lds_bytes, lds_limit_slot<N, CF, ENV, NEAR, LIN, COMP>());
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(s.grid), dim3(kDirsPerTile * kWaveSize), s.lds_bytes, stream, p);
     return hipGetLastError();
 }
@@ -548,13 +565,8 @@ template <int N, bool CF, bool ENV, bool NEAR>
 hipError_t launch_batch_one(const BatchParams &bp, unsigned grid, size_t lds, hipStream_t stream)
 {
     auto fn = dmas_batch_kernel<N, CF, ENV, NEAR>;
-    static size_t lds_set = 64 * 1024;
-    if (lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_set = lds;
-    }
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), lds, lds_limit_slot<N, CF, ENV, NEAR, true, true>());
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kDirsPerTile * kWaveSize), lds, stream, bp);
     return hipGetLastError();
 }

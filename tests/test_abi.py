@@ -153,3 +153,14 @@ def test_unbuilt_combinations_reported(lib):
     d, keep = _desc(lib, geometry=1, compensated=1)
     h = ctypes.c_void_p()
     assert lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(h)) == 2
+
+
+def test_delay_span_limit(lib):
+    """Geometry whose delays would not fit the kernel's integer sample offsets is rejected."""
+    far = np.array([[1.0e6, 0.0, 0.0]] * 4)
+    d, keep = _desc(lib)
+    keep.append(far)
+    d.mic_pos = far.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    assert lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(h)) == 1
+    assert b"samples of delay" in lib.dmas_last_error()
