@@ -530,6 +530,17 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
         if ((e = hipHostMalloc(&s->h_tables[i], s->table_bytes, hipHostMallocDefault)) != hipSuccess)
             return fail_all(e, "batch table (host)");
     }
+    // Touch every stream once so that their hardware queues exist before the
+    // first frame arrives (created lazily otherwise, stalling the scheduler).
+    for (int i = 0; i < s->nstreams; ++i) {
+        if ((e = hipMemsetAsync(s->d_tables[i], 0, kAlign, s->streams[i])) != hipSuccess) return fail_all(e, "stream warm-up");
+        if ((e = hipEventRecord(s->launches[i].done, s->streams[i])) != hipSuccess) return fail_all(e, "stream warm-up");
+    }
+    if ((e = hipMemcpyAsync(s->d_tables[0], s->h_tables[0], kAlign, hipMemcpyHostToDevice, s->copy_stream)) != hipSuccess)
+        return fail_all(e, "copy stream warm-up");
+    for (hipStream_t st : s->streams)
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_all(e, "stream warm-up");
+    if ((e = hipStreamSynchronize(s->copy_stream)) != hipSuccess) return fail_all(e, "copy stream warm-up");
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return DMAS_OK;
