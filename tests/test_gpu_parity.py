@@ -339,3 +339,19 @@ def test_plan_rejects_bad_pipeline_options():
     with _plan(f) as plan:
         with pytest.raises(DmasError):
             plan.matched_filter(torch.zeros((8, 100), dtype=torch.float32, device="cuda"))
+
+
+@pytest.mark.parametrize("pick", [0, 1, 2])
+def test_serving_mix_full_size_sampled_rows(pick):
+    """Full-size frames of the serving mix (16/32/64 mics, up to 8192 x 16384), oracle on sampled rows."""
+    rng = np.random.default_rng(200 + pick)
+    M, D, T, n = [(64, 8192, 16384, 5), (16, 1024, 16384, 3), (32, 4096, 8192, 3)][pick]
+    dia = [0.20, 0.06, 0.12][pick]
+    mics = synth.disc_array(rng, M, dia, min_spacing=0.003)
+    n_el = {8192: 64, 1024: 16, 4096: 32}[D]
+    dirs = synth.az_el_grid(np.linspace(-90, 90, D // n_el), np.linspace(-45, 45, n_el))
+    f = synth.echo_frame(rng, mics, dirs, T, 10, n)
+    rows = _sample_rows(f, 8, 300 + pick)
+    _say(f"serving-mix frame M={M} D={D} T={T} n={n}")
+    res = _compare(f, f.x_f32(), rows=rows)
+    _say(f"serving-mix frame {res}")
