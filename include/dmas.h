@@ -77,6 +77,13 @@ typedef enum { DMAS_FARFIELD = 0, DMAS_NEARFIELD = 1 } dmas_geometry_t;
 typedef enum { DMAS_F32 = 0, DMAS_F16 = 1, DMAS_BF16 = 2 } dmas_dtype_t;
 typedef enum { DMAS_DELAY_NEAREST = 0, DMAS_DELAY_LINEAR = 1 } dmas_delay_mode_t;
 
+/* Accumulation of the power sums P_k of eq. (7) and of the CF sums of
+ * eq. (13). F32: plain FP32 sums. KAHAN: FP32 sums with one compensation term
+ * each. F64: the signed root is taken in FP32, its powers and all sums are
+ * formed in FP64, and eqs. (8)-(12) are evaluated in FP64. KAHAN and F64 are
+ * built for the far field with CF and nearest delays. */
+typedef enum { DMAS_ACCUM_F32 = 0, DMAS_ACCUM_KAHAN = 1, DMAS_ACCUM_F64 = 2 } dmas_accumulate_t;
+
 /* Largest supported order n and envelope length L. */
 #define DMAS_MAX_ORDER 8
 #define DMAS_MAX_FIR_LEN 255
@@ -104,7 +111,7 @@ typedef struct {
     double fir_fc;         /* default low-pass cut-off in Hz; 0 selects 5000 */
     int32_t in_dtype;      /* dmas_dtype_t of d_x */
     int32_t ng_fp64;       /* 0/1: evaluate eqs. (8)-(12) in FP64 instead of FP32 */
-    int32_t compensated;   /* 0/1: compensated (Kahan) FP32 accumulation of the power sums */
+    int32_t compensated;   /* dmas_accumulate_t: accumulation of the power sums (0 = FP32) */
     int32_t delay_mode;    /* dmas_delay_mode_t */
     int32_t env_decimation; /* envelope output keeps every k-th sample (k >= 1; 0 selects 1):
                                dmas_envelope writes D x ceil(T/k), element [p*ceil(T/k) + j]

@@ -317,7 +317,7 @@ dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scal
     const dmas::LaunchShape ls = dmas::shape_of(plan, env);
     hipError_t e = dmas::launch_plan(plan->order, &kp, ls, static_cast<hipStream_t>(stream));
     if (e == hipErrorNotSupported)
-        return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d linear=%d comp=%d",
+        return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d linear=%d accumulate=%d",
                     plan->order, (int)plan->cf, (int)env, (int)plan->nearfield, (int)plan->linear,
                     (int)plan->compensated);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -385,8 +385,9 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         return fail(DMAS_ERR_INVALID_ARG, "unknown in_dtype %d", d->in_dtype);
     if (d->delay_mode != DMAS_DELAY_NEAREST && d->delay_mode != DMAS_DELAY_LINEAR)
         return fail(DMAS_ERR_INVALID_ARG, "unknown delay_mode %d", d->delay_mode);
-    if ((d->ng_fp64 != 0 && d->ng_fp64 != 1) || (d->compensated != 0 && d->compensated != 1))
-        return fail(DMAS_ERR_INVALID_ARG, "ng_fp64 and compensated must be 0 or 1");
+    if (d->ng_fp64 != 0 && d->ng_fp64 != 1) return fail(DMAS_ERR_INVALID_ARG, "ng_fp64 must be 0 or 1");
+    if (d->compensated < DMAS_ACCUM_F32 || d->compensated > DMAS_ACCUM_F64)
+        return fail(DMAS_ERR_INVALID_ARG, "compensated must be 0 (FP32), 1 (Kahan) or 2 (FP64)");
     if (!(d->fs > 0.0) || !std::isfinite(d->fs)) return fail(DMAS_ERR_INVALID_ARG, "fs must be > 0");
     const double c = d->c == 0.0 ? 343.0 : d->c;
     if (!(c > 0.0) || !std::isfinite(c)) return fail(DMAS_ERR_INVALID_ARG, "c must be > 0");
@@ -424,11 +425,11 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
             return fail(DMAS_ERR_INVALID_ARG, "geometry spans %.3g samples of delay; at most 1e8 is supported", span);
     }
     if (d->compensated && (d->geometry != DMAS_FARFIELD || !d->use_cf))
-        return fail(DMAS_ERR_UNSUPPORTED, "compensated accumulation is built for far field with CF only");
+        return fail(DMAS_ERR_UNSUPPORTED, "Kahan and FP64 accumulation are built for far field with CF only");
     if (d->delay_mode == DMAS_DELAY_LINEAR && !d->use_cf)
         return fail(DMAS_ERR_UNSUPPORTED, "linear delays are built with CF only");
     if (d->delay_mode == DMAS_DELAY_LINEAR && d->compensated)
-        return fail(DMAS_ERR_UNSUPPORTED, "linear delays with compensated sums are not built");
+        return fail(DMAS_ERR_UNSUPPORTED, "linear delays are built with FP32 accumulation only");
     const int decim = d->env_decimation == 0 ? 1 : d->env_decimation;
     if (decim < 1 || decim > T) return fail(DMAS_ERR_INVALID_ARG, "env_decimation %d must lie in 1..T", decim);
     if (d->mf_len < 0 || d->mf_len > DMAS_MAX_MF_LEN || (d->mf_pulse && d->mf_len < 1) || (!d->mf_pulse && d->mf_len))
@@ -459,7 +460,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->cf = d->use_cf != 0;
     p->nearfield = d->geometry == DMAS_NEARFIELD;
     p->linear = d->delay_mode == DMAS_DELAY_LINEAR;
-    p->compensated = d->compensated != 0;
+    p->compensated = d->compensated;
     p->ng_fp64 = d->ng_fp64;
     p->dtype = d->in_dtype;
     p->fs = d->fs;

@@ -50,7 +50,7 @@ struct LaunchShape {
     bool env;
     bool nearfield;
     bool linear;              // linear fractional-delay interpolation
-    bool compensated;         // Kahan accumulation of the power sums
+    int accumulate;           // power-sum accumulation: 0 FP32, 1 Kahan FP32, 2 FP64
     unsigned grid;            // workgroups
     size_t lds_bytes;         // dynamic LDS
 };

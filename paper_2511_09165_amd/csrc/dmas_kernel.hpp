@@ -35,6 +35,7 @@
 #include <hip/hip_fp16.h>
 
 #include <atomic>
+#include <type_traits>
 
 #include "dmas_internal.hpp"
 
@@ -159,32 +160,41 @@ __device__ __forceinline__ void stage_row(float *__restrict__ dst, const void *_
 //                      s^N = x for odd N and |x| for even N
 //   a                : sum x (only needed separately for even N with CF)
 //   b                : sum x^2 (CF only)
-// With COMP, each sum carries a Kahan compensation term.
+// Accumulation modes: kAccF32 plain FP32 sums; kAccKahan FP32 sums with a
+// Kahan compensation term each; kAccF64 powers and sums in FP64 from the FP32
+// root (CDNA4 issues FP64 vector add/mul/FMA at the non-packed FP32 rate, so
+// this costs only the conversions).
 // ---------------------------------------------------------------------------
-template <int N, bool CF, bool COMP>
+enum : int { kAccF32 = 0, kAccKahan = 1, kAccF64 = 2 };
+
+template <int ACC>
+using AccType = typename std::conditional<ACC == kAccF64, double, float>::type;
+
+template <int N, bool CF, int ACC>
 struct Acc {
-    float p[N + 1];
-    float a, b;
-    float cp[COMP ? N + 1 : 1];
+    using T = AccType<ACC>;
+    T p[N + 1];
+    T a, b;
+    float cp[ACC == kAccKahan ? N + 1 : 1];
     float ca, cb;
 
     __device__ __forceinline__ void zero()
     {
 #pragma unroll
-        for (int k = 0; k <= N; ++k) p[k] = 0.0f;
-        a = b = 0.0f;
+        for (int k = 0; k <= N; ++k) p[k] = T(0);
+        a = b = T(0);
 #pragma unroll
-        for (int k = 0; k < (COMP ? N + 1 : 1); ++k) cp[k] = 0.0f;
+        for (int k = 0; k < (ACC == kAccKahan ? N + 1 : 1); ++k) cp[k] = 0.0f;
         ca = cb = 0.0f;
     }
 };
 
-template <bool COMP>
-__device__ __forceinline__ void acc_add(float &sum, float &comp, float term)
+template <int ACC, typename T>
+__device__ __forceinline__ void acc_add(T &sum, float &comp, T term)
 {
-    if constexpr (COMP) {
-        const float y = term - comp;
-        const float t = sum + y;
+    if constexpr (ACC == kAccKahan) {
+        const T y = term - comp;
+        const T t = sum + y;
         comp = (t - sum) - y;
         sum = t;
     } else {
@@ -192,12 +202,15 @@ __device__ __forceinline__ void acc_add(float &sum, float &comp, float term)
     }
 }
 
-template <int N, bool CF, bool COMP>
-__device__ __forceinline__ void accumulate(Acc<N, CF, COMP> &acc, float xv)
+template <int N, bool CF, int ACC>
+__device__ __forceinline__ void accumulate(Acc<N, CF, ACC> &acc, float xv)
 {
+    using T = AccType<ACC>;
+    constexpr bool KAHAN = ACC == kAccKahan;
     if constexpr (N == 1) {
-        acc_add<COMP>(acc.p[1], acc.cp[COMP ? 1 : 0], xv);
-        if constexpr (CF) acc_add<COMP>(acc.b, acc.cb, xv * xv);
+        const T x = T(xv);
+        acc_add<ACC>(acc.p[1], acc.cp[KAHAN ? 1 : 0], x);
+        if constexpr (CF) acc_add<ACC>(acc.b, acc.cb, x * x);
         return;
     } else {
         const float ax = __builtin_fabsf(xv);
@@ -208,16 +221,16 @@ __device__ __forceinline__ void accumulate(Acc<N, CF, COMP> &acc, float xv)
             // |x|^(1/N) = 2^(log2|x| / N); log2(0) = -inf gives r = 0
             r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(ax) * (1.0f / (float)N));
         }
-        float pw[N];                       // pw[k] = s^k, k = 1..N-1
-        pw[1] = __builtin_copysignf(r, xv);
-        if constexpr (N >= 3) pw[2] = r * r;
+        T pw[N];                       // pw[k] = s^k, k = 1..N-1
+        pw[1] = T(__builtin_copysignf(r, xv));
+        if constexpr (N >= 3) pw[2] = T(r) * T(r);
 #pragma unroll
         for (int k = 3; k < N; ++k) pw[k] = (k & 1) ? pw[k - 1] * pw[1] : pw[k / 2] * pw[k / 2];
 #pragma unroll
-        for (int k = 1; k < N; ++k) acc_add<COMP>(acc.p[k], acc.cp[COMP ? k : 0], pw[k]);
-        acc_add<COMP>(acc.p[N], acc.cp[COMP ? N : 0], (N & 1) ? xv : ax);
-        if constexpr (CF && !(N & 1)) acc_add<COMP>(acc.a, acc.ca, xv);
-        if constexpr (CF) acc_add<COMP>(acc.b, acc.cb, xv * xv);
+        for (int k = 1; k < N; ++k) acc_add<ACC>(acc.p[k], acc.cp[KAHAN ? k : 0], pw[k]);
+        acc_add<ACC>(acc.p[N], acc.cp[KAHAN ? N : 0], T((N & 1) ? xv : ax));
+        if constexpr (CF && !(N & 1)) acc_add<ACC>(acc.a, acc.ca, T(xv));
+        if constexpr (CF) acc_add<ACC>(acc.b, acc.cb, T(xv) * T(xv));
     }
 }
 
@@ -261,26 +274,27 @@ __device__ __forceinline__ R newton_girard(const R *P)
     }
 }
 
-template <int N, bool CF, bool COMP>
-__device__ __forceinline__ float finish_pixel(const Acc<N, CF, COMP> &acc, const KernelParams &p)
+template <int N, bool CF, int ACC>
+__device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const KernelParams &p)
 {
+    constexpr bool KAHAN = ACC == kAccKahan;
     float e;
-    if (p.ng_fp64) {
+    if (ACC == kAccF64 || p.ng_fp64) {
         double P[N + 1];
 #pragma unroll
-        for (int k = 1; k <= N; ++k) P[k] = (double)acc.p[k] - (COMP ? (double)acc.cp[COMP ? k : 0] : 0.0);
+        for (int k = 1; k <= N; ++k) P[k] = (double)acc.p[k] - (KAHAN ? (double)acc.cp[KAHAN ? k : 0] : 0.0);
         e = (float)newton_girard<N, double>(P);
     } else {
         float P[N + 1];
 #pragma unroll
-        for (int k = 1; k <= N; ++k) P[k] = COMP ? acc.p[k] - acc.cp[COMP ? k : 0] : acc.p[k];
+        for (int k = 1; k <= N; ++k) P[k] = KAHAN ? (float)acc.p[k] - acc.cp[KAHAN ? k : 0] : (float)acc.p[k];
         e = newton_girard<N, float>(P);
     }
     if constexpr (CF) {
-        float sx = (N & 1) ? acc.p[N] : acc.a;
-        float sb = acc.b;
-        if constexpr (COMP) {
-            sx -= (N & 1) ? acc.cp[COMP ? N : 0] : acc.ca;
+        float sx = (float)((N & 1) ? acc.p[N] : acc.a);
+        float sb = (float)acc.b;
+        if constexpr (KAHAN) {
+            sx -= (N & 1) ? acc.cp[KAHAN ? N : 0] : acc.ca;
             sb -= acc.cb;
         }
         const float den = __builtin_fmaf((float)p.M, sb, p.cf_eps);
@@ -296,7 +310,7 @@ __device__ __forceinline__ float finish_pixel(const Acc<N, CF, COMP> &acc, const
 // the frame described by p. Shared by the single-frame and the multi-frame
 // (batched) kernels, so a pixel's arithmetic does not depend on how it was
 // launched.
-template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, bool COMP>
+template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, int ACC>
 __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile, const int seg,
                                           float *__restrict__ smem)
 {
@@ -367,7 +381,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 
     for (int ch = 0; ch < nchunks; ++ch) {
         const int tc = ystart + ch * C;
-        Acc<N, CF, COMP> acc[K];
+        Acc<N, CF, ACC> acc[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j].zero();
 
@@ -412,13 +426,13 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                         }
 #pragma unroll
                         for (int j = 0; j < K; ++j)
-                            accumulate<N, CF, COMP>(acc[j], __builtin_fmaf(fr, v1[j] - v0[j], v0[j]));
+                            accumulate<N, CF, ACC>(acc[j], __builtin_fmaf(fr, v1[j] - v0[j], v0[j]));
                     } else {
                         float v[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) v[j] = src[kWaveSize * j];
 #pragma unroll
-                        for (int j = 0; j < K; ++j) accumulate<N, CF, COMP>(acc[j], v[j]);
+                        for (int j = 0; j < K; ++j) accumulate<N, CF, ACC>(acc[j], v[j]);
                     }
                 }
             }
@@ -431,14 +445,14 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
-                const float y = finish_pixel<N, CF, COMP>(acc[j], p);
+                const float y = finish_pixel<N, CF, ACC>(acc[j], p);
                 if (t < g1) __builtin_nontemporal_store(y, p.out + orow + t);
             }
         } else {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
-                const float y = finish_pixel<N, CF, COMP>(acc[j], p);
+                const float y = finish_pixel<N, CF, ACC>(acc[j], p);
                 ring[2 * H + lane + kWaveSize * j] = (t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -490,12 +504,12 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 // Single-frame kernel: workgroup b covers tile b % num_tiles of segment
 // b / num_tiles (tiles fastest, so workgroups resident at the same time share
 // a time window of the channels).
-template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, bool COMP>
+template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, int ACC>
 __global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
 dmas_kernel(const KernelParams p)
 {
     extern __shared__ float smem[];
-    dmas_body<N, CF, ENV, NEAR, LINEAR, COMP>(p, blockIdx.x % p.num_tiles, blockIdx.x / p.num_tiles, smem);
+    dmas_body<N, CF, ENV, NEAR, LINEAR, ACC>(p, blockIdx.x % p.num_tiles, blockIdx.x / p.num_tiles, smem);
 }
 
 // Multi-frame kernel for the serving runtime: the batch lists the frames'
@@ -515,13 +529,17 @@ dmas_batch_kernel(const BatchParams bp)
     }
     const KernelParams p = bp.frames[lo];
     const int local = b - bp.starts[lo];
-    dmas_body<N, CF, ENV, NEAR, false, false>(p, local % p.num_tiles, local / p.num_tiles, smem);
+    dmas_body<N, CF, ENV, NEAR, false, kAccF32>(p, local % p.num_tiles, local / p.num_tiles, smem);
 }
 
 // Dynamic LDS above 64 KiB must be allowed per kernel; the allowed size only
 // grows. One counter per kernel instantiation, safe to share between host
 // threads (a lost race only repeats the call).
-template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
+// The batch kernels use the accumulation tag kBatchSlot, which no
+// single-frame instantiation has.
+constexpr int kBatchSlot = -1;
+
+template <int N, bool CF, bool ENV, bool NEAR, bool LIN, int ACC>
 std::atomic<size_t> &lds_limit_slot()
 {
     static std::atomic<size_t> allowed{64 * 1024};
@@ -541,22 +559,22 @@ inline hipError_t raise_lds_limit(const void *fn, size_t lds, std::atomic<size_t
 
 // Host-side launcher for one order: picks the instantiation for the flags.
 // Instantiated: every (CF, envelope, geometry) with nearest delays; linear
-// delays with CF; compensated sums for the far field with CF.
-template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
+// delays with CF; Kahan and FP64 accumulation for the far field with CF.
+template <int N, bool CF, bool ENV, bool NEAR, bool LIN, int ACC>
 hipError_t launch_one(const KernelParams &p, const LaunchShape &s, hipStream_t stream)
 {
-    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, COMP>;
-    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), s.lds_bytes, lds_limit_slot<N, CF, ENV, NEAR, LIN, COMP>());
+    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, ACC>;
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), s.lds_bytes, lds_limit_slot<N, CF, ENV, NEAR, LIN, ACC>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(s.grid), dim3(kDirsPerTile * kWaveSize), s.lds_bytes, stream, p);
     return hipGetLastError();
 }
 
 // Resident workgroups per CU for this instantiation and LDS size.
-template <int N, bool CF, bool ENV, bool NEAR, bool LIN, bool COMP>
+template <int N, bool CF, bool ENV, bool NEAR, bool LIN, int ACC>
 hipError_t occupancy_one(const LaunchShape &s, int *blocks)
 {
-    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, COMP>;
+    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, ACC>;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(fn),
                                                         kDirsPerTile * kWaveSize, s.lds_bytes);
 }
@@ -565,7 +583,7 @@ template <int N, bool CF, bool ENV, bool NEAR>
 hipError_t launch_batch_one(const BatchParams &bp, unsigned grid, size_t lds, hipStream_t stream)
 {
     auto fn = dmas_batch_kernel<N, CF, ENV, NEAR>;
-    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), lds, lds_limit_slot<N, CF, ENV, NEAR, true, true>());
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), lds, lds_limit_slot<N, CF, ENV, NEAR, true, kBatchSlot>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kDirsPerTile * kWaveSize), lds, stream, bp);
     return hipGetLastError();
@@ -590,25 +608,27 @@ hipError_t launch_batch_order(const BatchParams &bp, bool cf, bool env, bool nea
 template <int N>
 hipError_t launch_order(const KernelParams *p, const LaunchShape &s, hipStream_t stream, int *blocks)
 {
-#define DMAS_CASE(CF, ENV, NEAR, LIN, COMP)                                                  \
+#define DMAS_CASE(CF, ENV, NEAR, LIN, ACC)                                                   \
     if (s.cf == CF && s.env == ENV && s.nearfield == NEAR && s.linear == LIN &&           \
-        s.compensated == COMP)                                                            \
-        return p ? launch_one<N, CF, ENV, NEAR, LIN, COMP>(*p, s, stream)                 \
-                 : occupancy_one<N, CF, ENV, NEAR, LIN, COMP>(s, blocks);
-    DMAS_CASE(false, false, false, false, false)
-    DMAS_CASE(false, true, false, false, false)
-    DMAS_CASE(true, false, false, false, false)
-    DMAS_CASE(true, true, false, false, false)
-    DMAS_CASE(false, false, true, false, false)
-    DMAS_CASE(false, true, true, false, false)
-    DMAS_CASE(true, false, true, false, false)
-    DMAS_CASE(true, true, true, false, false)
-    DMAS_CASE(true, false, false, true, false)
-    DMAS_CASE(true, true, false, true, false)
-    DMAS_CASE(true, false, true, true, false)
-    DMAS_CASE(true, true, true, true, false)
-    DMAS_CASE(true, false, false, false, true)
-    DMAS_CASE(true, true, false, false, true)
+        s.accumulate == ACC)                                                              \
+        return p ? launch_one<N, CF, ENV, NEAR, LIN, ACC>(*p, s, stream)                  \
+                 : occupancy_one<N, CF, ENV, NEAR, LIN, ACC>(s, blocks);
+    DMAS_CASE(false, false, false, false, kAccF32)
+    DMAS_CASE(false, true, false, false, kAccF32)
+    DMAS_CASE(true, false, false, false, kAccF32)
+    DMAS_CASE(true, true, false, false, kAccF32)
+    DMAS_CASE(false, false, true, false, kAccF32)
+    DMAS_CASE(false, true, true, false, kAccF32)
+    DMAS_CASE(true, false, true, false, kAccF32)
+    DMAS_CASE(true, true, true, false, kAccF32)
+    DMAS_CASE(true, false, false, true, kAccF32)
+    DMAS_CASE(true, true, false, true, kAccF32)
+    DMAS_CASE(true, false, true, true, kAccF32)
+    DMAS_CASE(true, true, true, true, kAccF32)
+    DMAS_CASE(true, false, false, false, kAccKahan)
+    DMAS_CASE(true, true, false, false, kAccKahan)
+    DMAS_CASE(true, false, false, false, kAccF64)
+    DMAS_CASE(true, true, false, false, kAccF64)
 #undef DMAS_CASE
     return hipErrorNotSupported;
 }

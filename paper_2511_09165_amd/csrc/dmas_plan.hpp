@@ -12,7 +12,8 @@
 struct dmas_plan_s {
     int device = 0;
     int M = 0, T = 0, D = 0, order = 0;
-    bool cf = true, nearfield = false, linear = false, compensated = false;
+    bool cf = true, nearfield = false, linear = false;
+    int compensated = 0;   // 0 FP32 sums, 1 Kahan FP32, 2 FP64
     int ng_fp64 = 0;
     int dtype = DMAS_F32;
     double fs = 0, c = 0;
@@ -76,7 +77,7 @@ inline LaunchShape shape_of(const dmas_plan_s *p, bool env)
     ls.env = env;
     ls.nearfield = p->nearfield;
     ls.linear = p->linear;
-    ls.compensated = p->compensated;
+    ls.accumulate = p->compensated;
     ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
     ls.lds_bytes = env ? p->lds_env : p->lds_rf;
     return ls;

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "DMAS_OK", 1: "DMAS_ERR_INVALID_ARG", 2: "DMAS_ERR_UNSUPPORTE
 SUBMIT_ENVELOPE = 1
 SUBMIT_AUTO_RELEASE = 2
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+ACCUMULATE = {"f32": 0, "kahan": 1, "f64": 2}   # dmas_accumulate_t
 EXPORTED = ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
             "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass",
             "dmas_matched_filter", "dmas_last_error", "dmas_version",
@@ -158,13 +159,14 @@ class Plan:
 
     Parameters follow ``dmas_plan_desc_t``. ``mic_pos`` is (M, 3) metres;
     ``dirs`` is (D, 3) unit vectors (far field) or voxel centres (near field).
+    ``accumulate`` is "f32", "kahan" or "f64" (``compensated=True`` is "kahan").
     """
 
     def __init__(self, mic_pos, dirs, num_samples: int, order: int, fs: float, c: float = 343.0,
                  use_cf: bool = True, nearfield: bool = False, fir_taps=None, fir_len: int = 63,
                  fir_fc: float = 5000.0, in_dtype: str = "f32", ng_fp64: bool = False,
                  compensated: bool = False, linear: bool = False, cf_eps: float = 1e-20,
-                 env_decimation: int = 1, mf_pulse=None):
+                 env_decimation: int = 1, mf_pulse=None, accumulate: Optional[str] = None):
         lib = load_library()
         self._lib = lib
         self._handle = ctypes.c_void_p()
@@ -190,7 +192,13 @@ class Plan:
             d.fir_len = int(fir_len)
         d.fir_fc = float(fir_fc)
         d.in_dtype = DTYPES[in_dtype]
-        d.ng_fp64, d.compensated, d.delay_mode = int(bool(ng_fp64)), int(bool(compensated)), int(bool(linear))
+        if accumulate is None:
+            accumulate = "kahan" if compensated else "f32"
+        elif compensated and accumulate != "kahan":
+            raise ValueError("compensated=True asks for accumulate='kahan'")
+        if accumulate not in ACCUMULATE:
+            raise ValueError(f"accumulate must be one of {sorted(ACCUMULATE)}")
+        d.ng_fp64, d.compensated, d.delay_mode = int(bool(ng_fp64)), ACCUMULATE[accumulate], int(bool(linear))
         d.env_decimation = int(env_decimation)
         pulse = None
         if mf_pulse is not None:

@@ -150,9 +150,15 @@ def test_null_arguments(lib):
 
 
 def test_unbuilt_combinations_reported(lib):
-    d, keep = _desc(lib, geometry=1, compensated=1)
     h = ctypes.c_void_p()
-    assert lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(h)) == 2
+    for acc in (1, 2):
+        d, keep = _desc(lib, geometry=1, compensated=acc)
+        assert lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(h)) == 2
+        d, keep = _desc(lib, use_cf=0, compensated=acc)
+        assert lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(h)) == 2
+    d, keep = _desc(lib, compensated=3)
+    assert lib.dmas_plan_create(ctypes.byref(d), ctypes.byref(h)) == 1
+    assert b"compensated" in lib.dmas_last_error()
 
 
 def test_delay_span_limit(lib):

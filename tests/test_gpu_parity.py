@@ -249,7 +249,7 @@ def test_half_precision_storage(dtype):
 
 
 @pytest.mark.parametrize("variant", [dict(ng_fp64=True), dict(compensated=True),
-                                     dict(ng_fp64=True, compensated=True)])
+                                     dict(ng_fp64=True, compensated=True), dict(accumulate="f64")])
 @pytest.mark.parametrize("n", [2, 5, 7])
 def test_precision_variants(n, variant):
     f = synth.config3(order=n)

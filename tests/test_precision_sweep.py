@@ -1,4 +1,6 @@
-"""Mixed-precision sweep: storage FP32/FP16/BF16 x Newton-Girard FP32/FP64 x plain/Kahan sums, orders 2..7.
+"""Mixed-precision sweep, orders 2..7: storage FP32/FP16/BF16 x accumulation
+forms (FP32 sums with FP32 or FP64 Newton-Girard, Kahan FP32 sums with either,
+FP64 sums with FP64 Newton-Girard).
 
 Errors are measured against the FP64 oracle evaluated on the original FP64
 channel data (so storage rounding is part of each form's error):
@@ -24,6 +26,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 BOUND = {"f32": 1e-4, "f16": 2e-3, "bf16": 1.6e-2}
+FORMS = [("f32", False), ("f32", True), ("kahan", False), ("kahan", True), ("f64", True)]
 
 
 def _quantise(x: np.ndarray, dtype: str):
@@ -52,20 +55,19 @@ def test_precision_sweep():
         for dt in ("f32", "f16", "bf16"):
             xq, scale = _quantise(f.x, dt)
             xq = xq.cuda()
-            for ng64 in (False, True):
-                for comp in (False, True):
-                    print(f"[gpu] precision n={n} {dt} ng64={ng64} kahan={comp}", flush=True)
-                    with plan_for_frame(f, in_dtype=dt, ng_fp64=ng64, compensated=comp,
-                                        fir_taps=taps.astype(np.float32)) as plan:
-                        y = plan.beamform(xq, in_scale=scale).cpu().numpy().astype(np.float64)
-                        env = plan.envelope(xq, in_scale=scale).cpu().numpy().astype(np.float64)
-                    row = {"order": n, "storage": dt, "ng_fp64": ng64, "kahan": comp,
-                           "rf_rel": float(np.abs(y - y_ref).max() / np.abs(y_ref).max()),
-                           "env_rel": float(np.abs(env - env_ref).max() / env_ref.max()),
-                           "env_db": _db_dev(env, env_ref)}
-                    table.append(row)
+            for acc, ng64 in FORMS:
+                print(f"[gpu] precision n={n} {dt} accumulate={acc} ng64={ng64}", flush=True)
+                with plan_for_frame(f, in_dtype=dt, ng_fp64=ng64, accumulate=acc,
+                                    fir_taps=taps.astype(np.float32)) as plan:
+                    y = plan.beamform(xq, in_scale=scale).cpu().numpy().astype(np.float64)
+                    env = plan.envelope(xq, in_scale=scale).cpu().numpy().astype(np.float64)
+                row = {"order": n, "storage": dt, "accumulate": acc, "ng_fp64": ng64,
+                       "rf_rel": float(np.abs(y - y_ref).max() / np.abs(y_ref).max()),
+                       "env_rel": float(np.abs(env - env_ref).max() / env_ref.max()),
+                       "env_db": _db_dev(env, env_ref)}
+                table.append(row)
     for r in table:
-        print(f"n={r['order']} {r['storage']:>4} ng64={int(r['ng_fp64'])} kahan={int(r['kahan'])}: "
+        print(f"n={r['order']} {r['storage']:>4} acc={r['accumulate']:>5} ng64={int(r['ng_fp64'])}: "
               f"rf {r['rf_rel']:.2e} env {r['env_rel']:.2e} dB(-80) {r['env_db']:.2e}", flush=True)
     out_dir = os.environ.get("DMAS_REPORT_DIR")
     if out_dir:

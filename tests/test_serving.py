@@ -125,13 +125,13 @@ def test_one_launch_per_frame_mode():
 
 
 def test_unbatchable_plans_in_the_mix():
-    """Linear-delay and compensated plans are launched one by one among batched frames."""
+    """Linear-delay, Kahan and FP64-accumulation plans are launched one by one among batched frames."""
     from paper_2511_09165_amd import plan_for_frame
     frames = _mix(4, 6)
-    opts = [dict(), dict(linear=True), dict(), dict(compensated=True), dict(), dict()]
+    opts = [dict(), dict(linear=True), dict(), dict(compensated=True), dict(), dict(accumulate="f64")]
     plans = []
     for f, o in zip(frames, opts):
-        if o.get("compensated"):
+        if o.get("compensated") or o.get("accumulate"):
             f.nearfield = False
             f.dirs = synth.unit_vectors(np.linspace(-50, 50, f.num_dirs), np.zeros(f.num_dirs))
         plans.append(plan_for_frame(f, **o))
@@ -139,7 +139,7 @@ def test_unbatchable_plans_in_the_mix():
     outs, infos, stats = _run_server(frames, plans, hbm_budget=2 << 30, num_streams=2, max_batch=64)
     for a, b in zip(alone, outs):
         assert np.array_equal(a, b)
-    assert infos[1]["batch_frames"] == 1 and infos[3]["batch_frames"] == 1
+    assert infos[1]["batch_frames"] == 1 and infos[3]["batch_frames"] == 1 and infos[5]["batch_frames"] == 1
     for p in plans:
         p.close()
 
