@@ -41,22 +41,24 @@ TRANS_SLOTS = 2
 
 
 def mic_slots(n: int, cf: bool) -> int:
-    """VALU issue slots per microphone per output sample for order n (the method's minimum).
+    """VALU issue slots per microphone per output pixel for order n (the method's minimum).
 
-    Root: none (n = 1), sqrt (n = 2), or log2 + scale + exp2 (n >= 3); sign
-    transfer; the intermediate powers that cannot be fused into an FMA
-    accumulation; n power-sum accumulations (P_n is sum x or sum |x|); CF adds
-    sum x^2 (and sum x for even n).
+    With whole-sample delays the signed root of a delayed sample is the root of
+    a channel sample, so roots are counted once per channel sample
+    (``root_slots``), not per pixel. Per microphone and pixel remain: the
+    intermediate powers that cannot be fused into an FMA accumulation, n
+    power-sum accumulations (P_n is sum x or sum |x|), and for CF sum x^2 (and
+    sum x for even n).
     """
-    if n == 1:
-        root, sign, powers = 0, 0, 0
-    elif n == 2:
-        root, sign, powers = TRANS_SLOTS, 1, 0
-    else:
-        root, sign = 2 * TRANS_SLOTS + 1, 1
-        powers = {3: 0, 4: 1, 5: 1, 6: 2, 7: 2, 8: 3}[n]
+    powers = {1: 0, 2: 0, 3: 0, 4: 1, 5: 1, 6: 2, 7: 2, 8: 3}[n]
     accum = n + ((1 + (n % 2 == 0)) if cf else 0)
-    return root + sign + powers + accum
+    return powers + accum
+
+
+def root_slots(n: int) -> int:
+    """Slots per channel sample for its signed n-th root: none (n = 1), sqrt + sign (n = 2),
+    log2 + scale + exp2 + sign (n >= 3); transcendentals at TRANS_SLOTS."""
+    return 0 if n == 1 else (TRANS_SLOTS + 1 if n == 2 else 2 * TRANS_SLOTS + 2)
 
 
 def pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
@@ -64,6 +66,11 @@ def pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
     ng = {1: 0, 2: 3, 3: 7, 4: 11, 5: 15, 6: 21, 7: 28, 8: 36}[n]
     cf_ops = (4 + TRANS_SLOTS) if cf else 0      # square, fma, rcp, 2 mul
     return M * mic_slots(n, cf) + ng + cf_ops + 1 + fir_len
+
+
+def launch_slots(M: int, T: int, D: int, n: int, cf: bool, fir_len: int) -> int:
+    """Algorithmic slots of one frame: every pixel, plus every channel sample's root."""
+    return D * T * pixel_slots(M, n, cf, fir_len) + M * T * root_slots(n)
 
 
 def kernel_source_hash() -> str:
@@ -120,11 +127,13 @@ def _timed(launch, steps: int, warmup: int, stream):
     return wall * 1e3 / steps, ev0.elapsed_time(ev1) / steps
 
 
-def _roofline(slots_per_pixel: int, pixels: int, kernel_ms: float, traffic=None) -> dict:
-    achieved = slots_per_pixel * pixels / (kernel_ms * 1e-3)
+def _roofline(slots: int, pixels: int, kernel_ms: float, traffic=None) -> dict:
+    """VALU-issue roofline of one step: ``slots`` algorithmic slots over the step's kernel time
+    (root pass + beamformer, HIP events on the launch stream)."""
+    achieved = slots / (kernel_ms * 1e-3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12, "unit": "TOP/s",
             "frac": achieved / VALU_SLOTS_PER_S, "traffic": traffic, "kernel_ms": kernel_ms,
-            "ops_per_pixel": slots_per_pixel, "op": "VALU lane-instruction issue slot (transcendental = 2)"}
+            "ops_per_pixel": slots / pixels, "op": "VALU lane-instruction issue slot (transcendental = 2)"}
 
 
 def _base_record(args, value, ms_per_step, dtype, config) -> dict:
@@ -156,7 +165,8 @@ def bench_headline(args) -> dict:
                     "91x46 az/el directions, T=16384 samples at 450 kHz, 63-tap envelope FIR",
         "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len})
     rec["data"] = "synthetic (seeded eRTIS-like pulse-echo frame)"
-    rec["roofline"] = _roofline(pixel_slots(M, n, True, fir_len), pixels, kernel_ms, measured_traffic(workload_key))
+    rec["roofline"] = _roofline(launch_slots(M, T, D, n, True, fir_len), pixels, kernel_ms,
+                                measured_traffic(workload_key))
     if args.extra:
         reps = max(5, args.steps // 2)
         extra = {"rf_ms": _timed(lambda: plan.beamform(x, out=out), reps, 2, stream)[1]}
@@ -185,7 +195,7 @@ def bench_nearfield(args) -> dict:
         x = torch.from_numpy(frame.x_f32()).cuda()
         out = torch.empty((D, T), dtype=torch.float32, device="cuda")
         steps = max(3, args.steps // 10)
-        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, 2,
+        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, max(2, args.warmup // 20),
                                         torch.cuda.current_stream())
         info = plan.info()
     pixels = D * T
@@ -195,7 +205,7 @@ def bench_nearfield(args) -> dict:
         "fir_len": fir_len})
     rec["metric"] = "direction*samples/sec, order-3 DMAS+CF, 1024 mics, near field"
     rec["steps"] = steps
-    rec["roofline"] = _roofline(pixel_slots(M, n, True, fir_len), pixels, kernel_ms)
+    rec["roofline"] = _roofline(launch_slots(M, T, D, n, True, fir_len), pixels, kernel_ms)
     rec["extra"] = {"plan": info}
     return rec
 
@@ -321,8 +331,8 @@ def bench_serving(args) -> list:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=200, help="untimed steps first (clocks settle in ~100 ms)")
     ap.add_argument("--serving-rates", default="250,500,1000,1500,2000", help="offered frames/s (serving)")
     ap.add_argument("--serving-duration", type=float, default=2.0, help="seconds of arrivals per rate (serving)")
     ap.add_argument("--serving-pool", type=int, default=48, help="distinct frames in the serving pool")

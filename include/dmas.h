@@ -151,12 +151,25 @@ dmas_status_t dmas_plan_destroy(dmas_plan_t plan);
 
 dmas_status_t dmas_plan_query(dmas_plan_t plan, dmas_plan_info_t *info);
 
-/* DMAS-n (+CF) image, eqs. (1)-(14): writes d_y (D x T FP32, device). */
+/* DMAS-n (+CF) image, eqs. (1)-(14): writes d_y (D x T FP32, device).
+ * d_x: M x T channels of the plan's in_dtype, device, row-major (channel i
+ * at d_x + i*T). in_scale > 0 multiplies the result (the image is
+ * homogeneous of degree 1 in x, so scaled FP16/BF16 storage is undone here).
+ * Work is queued on `stream` (a hipStream_t; NULL = the null stream) and the
+ * call returns without waiting. With whole-sample delays and n >= 2 the
+ * call first takes every channel sample's signed root, eq. (4), into a
+ * plane of M x T (root, sample) FP32 pairs, which the beamformer then reads
+ * in place of d_x; the plane is allocated and freed in stream order from a
+ * device memory pool that the library keeps per device (M*T*8 bytes per call
+ * in flight), so one plan may be used on several streams at once. Errors:
+ * DMAS_ERR_INVALID_ARG (NULL pointers, in_scale, plan of another device),
+ * DMAS_ERR_OUT_OF_MEMORY (plane allocation), DMAS_ERR_DEVICE (launch). */
 dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y,
                             float in_scale, void *stream);
 
 /* DMAS-n (+CF) image followed by envelope detection in the same kernel:
- * writes d_env (D x ceil(T/k) FP32, device; k = env_decimation). */
+ * writes d_env (D x ceil(T/k) FP32, device; k = env_decimation). Arguments,
+ * root plane and errors as for dmas_beamform. */
 dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env,
                             float in_scale, void *stream);
 
@@ -186,8 +199,10 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  * direction grids, orders and lengths arrive while others are running:
  *   - submit copies the frame's input into pinned staging memory and queues it;
  *   - a scheduler thread admits queued frames in arrival order while their
- *     device input and output fit in the HBM budget (an arena allocated once),
- *     copies the input on a copy stream, and groups admitted frames into one
+ *     device input, root plane (M*T*8 bytes, plans with whole-sample delays
+ *     and n >= 2) and output fit in the HBM budget (an arena allocated once),
+ *     copies the input and fills the root plane on a copy stream, and groups
+ *     admitted frames into one
  *     multi-frame launch (frames with the same CF / envelope / geometry flags,
  *     nearest delays, plain sums; others are launched one by one) on the next
  *     free compute stream, so a new batch starts while earlier ones finish;
@@ -200,7 +215,7 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
 typedef struct dmas_server_s *dmas_server_t;
 
 typedef struct {
-    int64_t hbm_budget_bytes;  /* device memory for admitted frames' inputs + outputs (> 0) */
+    int64_t hbm_budget_bytes;  /* device memory for admitted frames' inputs, root planes and outputs (> 0) */
     int64_t staging_bytes;     /* pinned host memory for queued inputs; 0 selects 256 MiB */
     int32_t num_streams;       /* launches in flight at once; 0 selects 2 */
     int32_t max_batch_frames;  /* frames per launch; 0 selects 64; 1 = one plain launch per frame */
@@ -239,7 +254,7 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *desc, dmas_server_t *
 
 /* Queue one frame. h_x: host memory, M x T of the plan's in_dtype, copied
  * before return. arrival: the request's arrival time for latency accounting
- * (< 0: now). A frame whose input + output exceed the budget is
+ * (< 0: now). A frame whose input + root plane + output exceed the budget is
  * DMAS_ERR_INVALID_ARG; full staging is DMAS_ERR_BUSY (nothing queued). */
 dmas_status_t dmas_server_submit(dmas_server_t srv, dmas_plan_t plan, const void *h_x, float in_scale,
                                  int32_t flags, double arrival, uint64_t *ticket);

@@ -302,6 +302,44 @@ std::vector<int32_t> make_tiles(const dmas_plan_desc_t *d, bool nearfield, doubl
 
 
 
+// Root planes live in a memory pool of the library's own on each device,
+// allocated and freed in stream order around each launch, so that calls on
+// several streams never share one plane and the pool keeps the memory for
+// the next call instead of returning it to the device.
+std::mutex g_pool_mutex;
+std::vector<hipMemPool_t> g_pools;
+
+hipError_t device_pool(int dev, hipMemPool_t *out)
+{
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    if (g_pools.empty()) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess) return e;
+        g_pools.assign((size_t)std::max(n, 1), nullptr);
+    }
+    if (dev < 0 || dev >= (int)g_pools.size()) return hipErrorInvalidDevice;
+    if (!g_pools[dev]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        hipError_t e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return e;
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) {
+            (void)hipMemPoolDestroy(pool);
+            return e;
+        }
+        g_pools[dev] = pool;
+    }
+    *out = g_pools[dev];
+    return hipSuccess;
+}
+
 dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scale, void *stream,
                   bool env)
 {
@@ -313,9 +351,28 @@ dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scal
     if (hipGetDevice(&cur) != hipSuccess || cur != plan->device)
         return fail(DMAS_ERR_INVALID_ARG, "plan belongs to device %d but device %d is current", plan->device,
                     cur);
-    const dmas::KernelParams kp = dmas::make_params(plan, d_x, d_out, in_scale, env);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float2 *plane = nullptr;
+    hipError_t e = hipSuccess;
+    if (plan->roots) {
+        hipMemPool_t pool = nullptr;
+        e = device_pool(plan->device, &pool);
+        if (e != hipSuccess) return hip_fail(e, "root-plane memory pool");
+        e = hipMallocFromPoolAsync(reinterpret_cast<void **>(&plane), dmas::plane_bytes(plan), pool, st);
+        if (e != hipSuccess) return hip_fail(e, "root-plane allocation");
+        e = dmas::stage_roots(plan, d_x, plane, st);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(plane, st);
+            return hip_fail(e, "root-plane launch");
+        }
+    }
+    const dmas::KernelParams kp = dmas::make_params(plan, d_x, plane, d_out, in_scale, env);
     const dmas::LaunchShape ls = dmas::shape_of(plan, env);
-    hipError_t e = dmas::launch_plan(plan->order, &kp, ls, static_cast<hipStream_t>(stream));
+    e = dmas::launch_plan(plan->order, &kp, ls, st);
+    if (plane) {
+        const hipError_t ef = hipFreeAsync(plane, st);
+        if (e == hipSuccess) e = ef;
+    }
     if (e == hipErrorNotSupported)
         return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d linear=%d accumulate=%d",
                     plan->order, (int)plan->cf, (int)env, (int)plan->nearfield, (int)plan->linear,
@@ -460,6 +517,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->cf = d->use_cf != 0;
     p->nearfield = d->geometry == DMAS_NEARFIELD;
     p->linear = d->delay_mode == DMAS_DELAY_LINEAR;
+    p->roots = n >= 2 && !p->linear;
     p->compensated = d->compensated;
     p->ng_fp64 = d->ng_fp64;
     p->dtype = d->in_dtype;
@@ -476,7 +534,8 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->num_tiles = (int)(tiles.size() / W);
 
     std::vector<double> taps_d;
-    std::vector<float> taps((size_t)L);
+    // zero-padded to a multiple of 4: the envelope FIR reads taps in groups of 4
+    std::vector<float> taps((size_t)dmas::fir_taps_padded(L), 0.0f);
     if (d->fir_taps) {
         std::copy(d->fir_taps, d->fir_taps + L, taps.begin());
     } else {
@@ -495,7 +554,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     if ((st = dev_copy((void **)&p->d_mic, d->mic_pos, sizeof(double) * 3 * M, "mic_pos")) != DMAS_OK ||
         (st = dev_copy((void **)&p->d_dirs, d->dirs, sizeof(double) * 3 * (size_t)D, "dirs")) != DMAS_OK ||
         (st = dev_copy((void **)&p->d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(), "tiles")) != DMAS_OK ||
-        (st = dev_copy((void **)&p->d_taps, taps.data(), sizeof(float) * L, "taps")) != DMAS_OK ||
+        (st = dev_copy((void **)&p->d_taps, taps.data(), sizeof(float) * taps.size(), "taps")) != DMAS_OK ||
         (p->mf_len && (st = dev_copy((void **)&p->d_pulse, d->mf_pulse, sizeof(float) * p->mf_len, "pulse")) != DMAS_OK)) {
         plan_free(p);
         return st;
@@ -532,12 +591,15 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
     p->row = (p->row + 3) & ~3;
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
-    const size_t ring_bytes = sizeof(float) * (size_t)W * (C + 2 * H);
+    const size_t ring_bytes = sizeof(float) * (size_t)W * dmas::ring_stride(H);
     const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
     // Microphones per LDS block: the largest block whose footprint lets three
     // workgroups share a CU (else two, else one). More blocks cost barriers and
     // delay evaluations; fewer resident workgroups cost latency hiding.
-    auto lds_for = [&](int m) { return fixed + ring_bytes + sizeof(float) * (size_t)m * p->row; };
+    // Window elements: (root, sample) pairs when the kernel stages roots
+    // (whole-sample delays, n >= 2), else samples.
+    const size_t elem = p->roots ? 2 * sizeof(float) : sizeof(float);
+    auto lds_for = [&](int m) { return fixed + ring_bytes + elem * (size_t)m * p->row; };
     const int mb_max = std::min(M, dmas::kMaxMicBlock);
     int mb = 0;
     for (int per_cu = 3; per_cu >= 1 && mb == 0; --per_cu)
@@ -553,7 +615,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
                     "direction tiles spread over %d samples: the channel window does not fit in LDS", p->halo);
     }
     p->mic_block = mb;
-    p->lds_rf = fixed + sizeof(float) * (size_t)mb * p->row;
+    p->lds_rf = fixed + elem * (size_t)mb * p->row;
     p->lds_env = p->lds_rf + ring_bytes;
 
     const char *fixed_seg = std::getenv("DMAS_SEGMENT");

@@ -15,6 +15,8 @@ constexpr int kMaxMicBlock = 64;   // microphones staged in LDS at once (<= wave
 // Everything a beamforming launch needs, passed by value as the kernel argument.
 struct KernelParams {
     const void *x;            // M x T channels (dtype below), device
+    const float2 *roots;      // M x T (signed root, sample) pairs, device; used by
+                              // plans that stage roots (whole-sample delays, n >= 2)
     float *out;               // D x T image, device
     const double *mic;        // M x 3, device
     const double *dirs;       // D x 3, device
@@ -61,6 +63,15 @@ constexpr int kDirsPerTile = 8;
 constexpr int kSamplesPerLane = 4;
 constexpr int kChunk = kWaveSize * kSamplesPerLane;
 
+// Envelope ring of one wave (floats): the |y| value of ring index i sits at
+// ring_pad(H) + i, for i in [0, kChunk + 2H). The pad (4 to 7 floats, zero)
+// puts index 2H on a 16-byte boundary and gives the FIR's lowest 16-byte
+// group read a zero block to land on; the stride keeps rings 16-byte aligned.
+__host__ __device__ constexpr int ring_pad(int H) { return 4 + (4 - (2 * H) % 4) % 4; }
+__host__ __device__ constexpr int ring_stride(int H) { return (ring_pad(H) + kChunk + 2 * H + 3) & ~3; }
+// Envelope taps on the device: fir_len taps, zero-padded to a multiple of 4.
+__host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; }
+
 // Batched launch over frames of order n with the given CF / envelope /
 // geometry flags (nearest delays, plain sums); grid = total workgroups.
 hipError_t launch_batch(int order, const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
@@ -73,6 +84,10 @@ hipError_t launch_batch_order5(const BatchParams &, bool, bool, bool, unsigned, 
 hipError_t launch_batch_order6(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
 hipError_t launch_batch_order7(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
 hipError_t launch_batch_order8(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+
+// Root plane of a frame: plane[e] = (sgn(x_e) |x_e|^(1/order), x_e) for the
+// count = M * T channel samples of x (storage type dtype), in FP32.
+hipError_t launch_roots(int order, int dtype, const void *x, float2 *plane, size_t count, hipStream_t stream);
 
 // Matched filter: out[i*T + t] = sum_{k<P} raw[i*T + t + k] * pulse[k].
 hipError_t launch_matched_filter(const float *raw, const float *pulse, int M, int T, int P, float *out,

@@ -153,6 +153,53 @@ __device__ __forceinline__ void stage_row(float *__restrict__ dst, const void *_
     }
 }
 
+// Signed n-th root of one sample, eq. (4): sgn(x) |x|^(1/n) in FP32.
+// |x|^(1/n) = 2^(log2|x| / n); log2(0) = -inf gives 0.
+template <int N>
+__device__ __forceinline__ float signed_root(float xv)
+{
+    const float ax = __builtin_fabsf(xv);
+    float r;
+    if constexpr (N == 2) r = __builtin_amdgcn_sqrtf(ax);
+    else r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(ax) * (1.0f / (float)N));
+    return __builtin_copysignf(r, xv);
+}
+
+// With whole-sample delays the root of a delayed sample is the root of a
+// channel sample: a separate pass takes it once per channel sample (the root
+// plane of (s, x) pairs), and the beamformer stages windows of that plane.
+template <int N, bool LINEAR>
+constexpr bool kStagesRoots = N >= 2 && !LINEAR;
+
+// Root plane: plane[e] = (signed_root(x_e), x_e) over count samples.
+template <int N, int DT>
+__global__ void __launch_bounds__(256) root_plane_kernel(const void *__restrict__ x, float2 *__restrict__ plane,
+                                                         size_t count)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
+        const float v = load_sample<DT>(x, e);
+        plane[e] = make_float2(signed_root<N>(v), v);
+    }
+}
+
+// One microphone's window [base, base + row) of the root plane starting at
+// element chan, (0, 0) outside [0, T) (the pair of a zero sample).
+__device__ __forceinline__ void stage_row_roots(float2 *__restrict__ dst, const float2 *__restrict__ plane,
+                                                size_t chan, int base, int row, int T, int lane)
+{
+    if (base >= 0 && base + row <= T) {
+        const float2 *src = plane + chan + (size_t)base + lane;
+        float2 *d = dst + lane;
+        for (int r = 0; r < row - lane; r += kWaveSize) d[r] = src[r];
+    } else {
+        for (int r = lane; r < row; r += kWaveSize) {
+            const int t = base + r;
+            dst[r] = (t >= 0 && t < T) ? plane[chan + (size_t)t] : make_float2(0.0f, 0.0f);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Power-sum accumulators for one output sample.
 //   p[k], k = 1..N-1 : P_k = sum_i s_i^k                        eq. (7)
@@ -202,8 +249,10 @@ __device__ __forceinline__ void acc_add(T &sum, float &comp, T term)
     }
 }
 
+// Adds one microphone's terms given its signed root sv = sgn(x)|x|^(1/N) and
+// its sample xv.
 template <int N, bool CF, int ACC>
-__device__ __forceinline__ void accumulate(Acc<N, CF, ACC> &acc, float xv)
+__device__ __forceinline__ void accumulate_root(Acc<N, CF, ACC> &acc, float sv, float xv)
 {
     using T = AccType<ACC>;
     constexpr bool KAHAN = ACC == kAccKahan;
@@ -213,25 +262,23 @@ __device__ __forceinline__ void accumulate(Acc<N, CF, ACC> &acc, float xv)
         if constexpr (CF) acc_add<ACC>(acc.b, acc.cb, x * x);
         return;
     } else {
-        const float ax = __builtin_fabsf(xv);
-        float r;
-        if constexpr (N == 2) {
-            r = __builtin_amdgcn_sqrtf(ax);
-        } else {
-            // |x|^(1/N) = 2^(log2|x| / N); log2(0) = -inf gives r = 0
-            r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(ax) * (1.0f / (float)N));
-        }
         T pw[N];                       // pw[k] = s^k, k = 1..N-1
-        pw[1] = T(__builtin_copysignf(r, xv));
-        if constexpr (N >= 3) pw[2] = T(r) * T(r);
+        pw[1] = T(sv);
+        if constexpr (N >= 3) pw[2] = pw[1] * pw[1];
 #pragma unroll
         for (int k = 3; k < N; ++k) pw[k] = (k & 1) ? pw[k - 1] * pw[1] : pw[k / 2] * pw[k / 2];
 #pragma unroll
         for (int k = 1; k < N; ++k) acc_add<ACC>(acc.p[k], acc.cp[KAHAN ? k : 0], pw[k]);
-        acc_add<ACC>(acc.p[N], acc.cp[KAHAN ? N : 0], T((N & 1) ? xv : ax));
+        acc_add<ACC>(acc.p[N], acc.cp[KAHAN ? N : 0], T((N & 1) ? xv : __builtin_fabsf(xv)));
         if constexpr (CF && !(N & 1)) acc_add<ACC>(acc.a, acc.ca, T(xv));
         if constexpr (CF) acc_add<ACC>(acc.b, acc.cb, T(xv) * T(xv));
     }
+}
+
+template <int N, bool CF, int ACC>
+__device__ __forceinline__ void accumulate(Acc<N, CF, ACC> &acc, float xv)
+{
+    accumulate_root<N, CF, ACC>(acc, N == 1 ? xv : signed_root<N>(xv), xv);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,11 +368,14 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
 
+    constexpr bool ROOTS = kStagesRoots<N, LINEAR>;
+    using Elem = typename std::conditional<ROOTS, float2, float>::type;
+
     const int H = ENV ? (p.fir_len - 1) / 2 : 0;
-    const int ring_len = C + 2 * H;
-    float *xwin = smem;                                            // mic_block x row
+    Elem *xwin = reinterpret_cast<Elem *>(smem);                   // mic_block x row
     int *dref_lds = reinterpret_cast<int *>(xwin + p.mic_block * p.row);  // kMaxMicBlock
-    float *ring = reinterpret_cast<float *>(dref_lds + kMaxMicBlock) + wave * ring_len;
+    float *ring_buf = reinterpret_cast<float *>(dref_lds + kMaxMicBlock) + wave * ring_stride(H);
+    float *ring = ring_buf + ring_pad(H);                          // ring[i], i in [0, C + 2H)
 
     const int dir = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W + wave]);
     const int dir0 = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W]);
@@ -344,16 +394,21 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int nblocks = (p.M + p.mic_block - 1) / p.mic_block;
     const int two_halo = 2 * p.halo;
 
-    // Per block of microphones: lane i of every wave computes its direction's
-    // delay for microphone i of the block; wave 0's direction is the tile's
-    // reference, so wave 0 publishes its delays for the staging step. After a
+    // Steering delays. With M <= 64 lane i of every wave computes its
+    // direction's delay for microphone i once, and wave 0 (the tile's
+    // reference direction) publishes its delays in LDS for the staging step.
+    // With more microphones the same is done per block of microphones (lane i
+    // holding microphone i of the block), once per block and chunk. After a
     // barrier each lane turns (delay - reference delay) into its LDS offset.
+    const bool all_mics = p.M <= kWaveSize;
     int mydw = 0;
     int myoff = 0;
-    float myfrac = 0.0f;
+    float myfrac = 0.0f;      // fraction of mydw's microphone (linear delays)
+    float myfrac_blk = 0.0f;  // fraction of microphone `lane` of the current block
     auto block_geometry = [&](int blk) {
         const int mic = blk * p.mic_block + lane;
-        if (lane < p.mic_block) {
+        const int nlanes = all_mics ? p.M : p.mic_block;
+        if (lane < nlanes) {
             if (mic < p.M) {
                 mydw = steer_whole<NEAR, LINEAR>(p.mic + 3 * mic, vdir, p.fs, p.c, &myfrac);
                 if (wave == 0) dref_lds[lane] = mydw;
@@ -362,21 +417,34 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             }
         }
     };
+    // Reference delay of microphone i of block blk.
+    auto dref_of = [&](int blk, int i) { return dref_lds[all_mics ? blk * p.mic_block + i : i]; };
     auto block_offsets = [&](int blk) {
+        const int mic = blk * p.mic_block + lane;
+        int dw = mydw;
+        float fr = myfrac;
+        if (all_mics) {
+            // this lane's microphone sits in lane `mic` of the cached delays
+            const int src = min(mic, p.M - 1) << 2;
+            dw = __builtin_amdgcn_ds_bpermute(src, mydw);
+            if constexpr (LINEAR)
+                fr = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, myfrac)));
+        }
         if (lane < p.mic_block) {
             int rel = 0;
-            if (blk * p.mic_block + lane < p.M)
-                rel = min(max(mydw - dref_lds[lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
+            if (mic < p.M)
+                rel = min(max(dw - dref_of(blk, lane) + p.halo, 0), two_halo);  // the measured halo keeps this in range
             myoff = lane * p.row + rel;
+            if constexpr (LINEAR) myfrac_blk = fr;
         }
     };
 
     // Copy the taps' positions: the FIR reads them through the scalar cache.
     const float *__restrict__ taps = p.taps;
 
-    if (nblocks == 1) block_geometry(0);
+    if (all_mics) block_geometry(0);
     if constexpr (ENV) {
-        for (int i = lane; i < 2 * H; i += kWaveSize) ring[i] = 0.0f;
+        for (int i = lane; i < ring_pad(H) + 2 * H; i += kWaveSize) ring_buf[i] = 0.0f;
     }
 
     for (int ch = 0; ch < nchunks; ++ch) {
@@ -386,25 +454,25 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         for (int j = 0; j < K; ++j) acc[j].zero();
 
         for (int blk = 0; blk < nblocks; ++blk) {
-            if (nblocks > 1) block_geometry(blk);
+            if (!all_mics) block_geometry(blk);
             __syncthreads();  // reference delays visible; previous block's reads done
             block_offsets(blk);
             // ---- stage this block's channel windows into LDS ----
             for (int i = wave; i < p.mic_block; i += W) {
                 const int mic = blk * p.mic_block + i;
-                float *dst = xwin + i * p.row;
+                Elem *dst = xwin + i * p.row;
                 if (mic < p.M) {
-                    const int base = tc + dref_lds[i] - p.halo;
+                    const int base = tc + dref_of(blk, i) - p.halo;
                     const size_t chan = (size_t)mic * (size_t)p.T;
-                    if (p.dtype == 0) {
-                        stage_row<0>(dst, p.x, chan, base, p.row, p.T, lane);
-                    } else if (p.dtype == 1) {
-                        stage_row<1>(dst, p.x, chan, base, p.row, p.T, lane);
+                    if constexpr (ROOTS) {
+                        stage_row_roots(dst, p.roots, chan, base, p.row, p.T, lane);
                     } else {
-                        stage_row<2>(dst, p.x, chan, base, p.row, p.T, lane);
+                        if (p.dtype == 0) stage_row<0>(dst, p.x, chan, base, p.row, p.T, lane);
+                        else if (p.dtype == 1) stage_row<1>(dst, p.x, chan, base, p.row, p.T, lane);
+                        else stage_row<2>(dst, p.x, chan, base, p.row, p.T, lane);
                     }
                 } else {
-                    for (int r = lane; r < p.row; r += kWaveSize) dst[r] = 0.0f;
+                    for (int r = lane; r < p.row; r += kWaveSize) dst[r] = Elem{};
                 }
             }
             __syncthreads();
@@ -414,10 +482,16 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 #pragma unroll 2
                 for (int i = 0; i < nm; ++i) {
                     const int off = __builtin_amdgcn_readlane(myoff, i);
-                    const float *src = xwin + off + lane;
-                    if constexpr (LINEAR) {
+                    const Elem *src = xwin + off + lane;
+                    if constexpr (ROOTS) {
+                        float2 v[K];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) v[j] = src[kWaveSize * j];
+#pragma unroll
+                        for (int j = 0; j < K; ++j) accumulate_root<N, CF, ACC>(acc[j], v[j].x, v[j].y);
+                    } else if constexpr (LINEAR) {
                         const float fr = __builtin_bit_cast(
-                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myfrac), i));
+                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myfrac_blk), i));
                         float v0[K], v1[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
@@ -458,20 +532,50 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             // env[t] for t = tc - H + o, o in [0, C): sum_k h[k] |y[t + H - k]|
+            //   = sum_k h[k] ring[2H + o - k].
+            // Lane l owns o = 4l + j, j < 4. Taps go in groups of 4: group g
+            // needs ring[2H + 4l - 4g - 3 .. 2H + 4l - 4g + 3], i.e. the 16-byte
+            // block `cur` (ring[2H + 4(l-g) .. +3]) and the block below it, so
+            // each group costs one 16-byte LDS read and 16 FMAs. Taps past
+            // fir_len are zero; the blocks they meet below the ring are the
+            // zeroed pad.
             if (p.env_decim == 1) {
-                float e[K];
-#pragma unroll
-                for (int j = 0; j < K; ++j) e[j] = 0.0f;
-                for (int k = 0; k < p.fir_len; ++k) {
-                    const float h = taps[k];
-                    const float *src = ring + 2 * H - k + lane;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) e[j] = __builtin_fmaf(h, src[kWaveSize * j], e[j]);
+                const float4 *rb4 = reinterpret_cast<const float4 *>(ring + 2 * H) + lane;
+                const int ngroups = fir_taps_padded(p.fir_len) / 4;
+                float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f, e3 = 0.0f;
+                float4 cur = rb4[0];
+                for (int g = 0; g < ngroups; ++g) {
+                    const float4 lo = rb4[-g - 1];
+                    const float h0 = taps[4 * g], h1 = taps[4 * g + 1], h2 = taps[4 * g + 2], h3 = taps[4 * g + 3];
+                    e0 = __builtin_fmaf(h0, cur.x, e0);
+                    e0 = __builtin_fmaf(h1, lo.w, e0);
+                    e0 = __builtin_fmaf(h2, lo.z, e0);
+                    e0 = __builtin_fmaf(h3, lo.y, e0);
+                    e1 = __builtin_fmaf(h0, cur.y, e1);
+                    e1 = __builtin_fmaf(h1, cur.x, e1);
+                    e1 = __builtin_fmaf(h2, lo.w, e1);
+                    e1 = __builtin_fmaf(h3, lo.z, e1);
+                    e2 = __builtin_fmaf(h0, cur.z, e2);
+                    e2 = __builtin_fmaf(h1, cur.y, e2);
+                    e2 = __builtin_fmaf(h2, cur.x, e2);
+                    e2 = __builtin_fmaf(h3, lo.w, e2);
+                    e3 = __builtin_fmaf(h0, cur.w, e3);
+                    e3 = __builtin_fmaf(h1, cur.z, e3);
+                    e3 = __builtin_fmaf(h2, cur.y, e3);
+                    e3 = __builtin_fmaf(h3, cur.x, e3);
+                    cur = lo;
                 }
+                const int t0 = tc - H + 4 * lane;   // a multiple of 4 (tc - H is one of 32)
+                float *dst = p.out + orow + t0;
+                if (t0 >= g0 && t0 + 3 < g1 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                    typedef float v4f __attribute__((ext_vector_type(4)));
+                    const v4f v = {e0, e1, e2, e3};
+                    __builtin_nontemporal_store(v, reinterpret_cast<v4f *>(dst));
+                } else {
+                    const float ev[4] = {e0, e1, e2, e3};
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const int t = tc - H + lane + kWaveSize * j;
-                    if (t >= g0 && t < g1) __builtin_nontemporal_store(e[j], p.out + orow + t);
+                    for (int j = 0; j < 4; ++j)
+                        if (t0 + j >= g0 && t0 + j < g1) __builtin_nontemporal_store(ev[j], dst + j);
                 }
             } else {
                 // Decimated envelope: only the outputs at t = j * env_decim, each

@@ -13,6 +13,7 @@ struct dmas_plan_s {
     int device = 0;
     int M = 0, T = 0, D = 0, order = 0;
     bool cf = true, nearfield = false, linear = false;
+    bool roots = false;    // kernel reads a root plane (whole-sample delays, n >= 2)
     int compensated = 0;   // 0 FP32 sums, 1 Kahan FP32, 2 FP64
     int ng_fp64 = 0;
     int dtype = DMAS_F32;
@@ -38,11 +39,26 @@ struct dmas_plan_s {
 
 namespace dmas {
 
-// Kernel arguments for one launch of `plan` on input d_x / output d_out.
-inline KernelParams make_params(const dmas_plan_s *plan, const void *d_x, float *d_out, float in_scale, bool env)
+// Device bytes of a frame's root plane (zero when the plan does not use one).
+inline size_t plane_bytes(const dmas_plan_s *plan)
+{
+    return plan->roots ? (size_t)plan->M * (size_t)plan->T * sizeof(float2) : 0;
+}
+
+// Fill the root plane of input d_x (plans with roots only).
+inline hipError_t stage_roots(const dmas_plan_s *plan, const void *d_x, float2 *d_plane, hipStream_t stream)
+{
+    return launch_roots(plan->order, plan->dtype, d_x, d_plane, (size_t)plan->M * (size_t)plan->T, stream);
+}
+
+// Kernel arguments for one launch of `plan` on input d_x (and its root plane
+// d_plane when the plan uses one) / output d_out.
+inline KernelParams make_params(const dmas_plan_s *plan, const void *d_x, const float2 *d_plane, float *d_out,
+                                float in_scale, bool env)
 {
     KernelParams kp{};
     kp.x = d_x;
+    kp.roots = d_plane;
     kp.out = d_out;
     kp.mic = plan->d_mic;
     kp.dirs = plan->d_dirs;

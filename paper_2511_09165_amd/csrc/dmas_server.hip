@@ -103,6 +103,7 @@ struct Frame {
     size_t stage_off = 0;
     bool staged = false;
     size_t in_off = 0, out_off = 0;
+    size_t plane_bytes = 0, plane_off = 0;   // root plane (plans that stage roots)
     bool on_device = false;
     hipEvent_t copied = nullptr;
     int state = kQueued;
@@ -121,11 +122,12 @@ struct Launch {
     double tail_start = 0;    // predicted start of its last device round
 };
 
-// Modelled VALU issue slots of one frame (per-microphone root and power sums,
-// Newton-Girard, CF and envelope per pixel); used only to predict durations.
+// Modelled VALU issue slots of one frame (per-microphone power sums,
+// Newton-Girard, CF and envelope per pixel; roots are taken once per channel
+// sample); used only to predict durations.
 double frame_work(const dmas_plan_s *p, bool env)
 {
-    const double per_mic = p->order == 1 ? 2.0 : p->order == 2 ? 7.0 : 8.0 + p->order;
+    const double per_mic = p->order == 1 ? 2.0 : p->roots ? 3.0 + p->order : 8.0 + p->order;
     return (double)p->D * p->T * (p->M * per_mic + 30.0 + (env ? p->fir_len : 0));
 }
 
@@ -212,11 +214,17 @@ struct dmas_server_s {
         info->pixels = (int64_t)f->plan->D * f->plan->T;   // beamformed pixels (before decimation)
     }
 
+    float2 *plane_of(const Frame *f) const
+    {
+        return f->plane_bytes ? reinterpret_cast<float2 *>(d_arena + f->plane_off) : nullptr;
+    }
+
     void free_device(Frame *f)
     {
         if (!f->on_device) return;
         arena.release(f->in_off, f->in_bytes);
         arena.release(f->out_off, f->out_bytes);
+        if (f->plane_bytes) arena.release(f->plane_off, f->plane_bytes);
         f->on_device = false;
     }
 
@@ -274,19 +282,27 @@ struct dmas_server_s {
         bool progress = false;
         while (!queued.empty()) {
             Frame *f = queued.front();
-            size_t in_off, out_off;
+            size_t in_off, out_off, plane_off = 0;
             if (!arena.alloc(f->in_bytes, &in_off)) break;
             if (!arena.alloc(f->out_bytes, &out_off)) {
                 arena.release(in_off, f->in_bytes);
                 break;
             }
+            if (f->plane_bytes && !arena.alloc(f->plane_bytes, &plane_off)) {
+                arena.release(in_off, f->in_bytes);
+                arena.release(out_off, f->out_bytes);
+                break;
+            }
             f->in_off = in_off;
             f->out_off = out_off;
+            f->plane_off = plane_off;
             f->on_device = true;
             hbm_peak = std::max(hbm_peak, arena.used());
             f->copied = get_event();
+            // input copy, then the root plane, both on the copy stream
             hipError_t e = hipMemcpyAsync(d_arena + in_off, h_staging + f->stage_off, f->in_bytes,
                                           hipMemcpyHostToDevice, copy_stream);
+            if (e == hipSuccess && f->plane_bytes) e = dmas::stage_roots(f->plan, d_arena + in_off, plane_of(f), copy_stream);
             if (e == hipSuccess && f->copied) e = hipEventRecord(f->copied, copy_stream);
             f->t_admit = now_s();
             queued.pop_front();
@@ -355,7 +371,8 @@ struct dmas_server_s {
                 if (group.size() == 1) {
                     Frame *f = group[0];
                     const dmas::KernelParams kp = dmas::make_params(
-                        f->plan, d_arena + f->in_off, reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale, f->env);
+                        f->plan, d_arena + f->in_off, plane_of(f), reinterpret_cast<float *>(d_arena + f->out_off),
+                        f->in_scale, f->env);
                     e = dmas::launch_plan(f->plan->order, &kp, dmas::shape_of(f->plan, f->env), st);
                 } else {
                     // Table layout: nf KernelParams, then nf int32 first-workgroup indices.
@@ -366,7 +383,7 @@ struct dmas_server_s {
                     size_t lds = 0;
                     for (int i = 0; i < nf; ++i) {
                         Frame *f = group[i];
-                        kp[i] = dmas::make_params(f->plan, d_arena + f->in_off,
+                        kp[i] = dmas::make_params(f->plan, d_arena + f->in_off, plane_of(f),
                                                   reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale, f->env);
                         starts[i] = (int32_t)total;
                         total += dmas::plan_workgroups(f->plan, f->env);
@@ -562,9 +579,10 @@ dmas_status_t dmas_server_submit(dmas_server_t s, dmas_plan_t plan, const void *
     f->in_bytes = (size_t)plan->M * plan->T * elem_size(plan->dtype);
     const size_t out_T = f->env ? (size_t)(plan->T + plan->env_decim - 1) / plan->env_decim : (size_t)plan->T;
     f->out_bytes = (size_t)plan->D * out_T * sizeof(float);
-    if (align_up(f->in_bytes) + align_up(f->out_bytes) > s->budget) {
+    f->plane_bytes = dmas::plane_bytes(plan);
+    if (align_up(f->in_bytes) + align_up(f->out_bytes) + align_up(f->plane_bytes) > s->budget) {
         delete f;
-        return srv_fail(DMAS_ERR_INVALID_ARG, "frame input + output exceed the server's HBM budget");
+        return srv_fail(DMAS_ERR_INVALID_ARG, "frame input, root plane and output exceed the server's HBM budget");
     }
     if (align_up(f->in_bytes) > s->staging) {
         delete f;

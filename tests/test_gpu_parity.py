@@ -331,6 +331,22 @@ def test_envelope_decimation(k):
     check_t1(dec, env_ref[:, ::k])
 
 
+@pytest.mark.parametrize("T", [1000, 997])
+@pytest.mark.parametrize("L", [1, 3, 5, 7, 9, 61, 63, 65, 127, 255])
+def test_envelope_fir_lengths(L, T):
+    """Envelope with arbitrary odd-length taps (both residues of (L-1)/2 mod 2, L mod 4 all classes),
+    on records whose rows are and are not 16-byte aligned in the output."""
+    f = synth.random_frame(np.random.default_rng(200 + L), 12, 21, T, 3)
+    taps = np.random.default_rng(300 + L).normal(size=L).astype(np.float32)
+    _say(f"fir L={L} T={T}")
+    env = _run(f, f.x_f32(), env=True, taps=taps)
+    y_ref = oracle.frame_rows(f, x=f.x_f32().astype(np.float64))
+    env_ref = oracle.envelope(y_ref, taps.astype(np.float64))
+    check_t1(env, env_ref)
+    dec = _run(f, f.x_f32(), env=True, taps=taps, env_decimation=3)
+    assert np.array_equal(dec, env[:, ::3])
+
+
 def test_plan_rejects_bad_pipeline_options():
     from paper_2511_09165_amd import DmasError
     f = synth.random_frame(np.random.default_rng(96), 8, 5, 100, 2)
