@@ -22,7 +22,7 @@ SOURCES = ["dmas_api.hip", "dmas_batch.hip", "dmas_server.hip", "dmas_mf.hip", "
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
-    "-ffp-contract=fast",
+    "-ffp-contract=fast-honor-pragmas",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(HERE, "..", "include"),

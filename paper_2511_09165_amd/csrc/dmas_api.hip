@@ -25,6 +25,10 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Largest per-tile delay table a plan builds (bytes); larger plans evaluate
+// the delays per block of microphones instead.
+constexpr size_t kMaxTileTableBytes = size_t(2) << 30;
+
 dmas_status_t fail(dmas_status_t st, const char *fmt, ...)
 {
     char buf[512];
@@ -98,6 +102,34 @@ tile_spread_kernel(const double *__restrict__ mic, const double *__restrict__ di
     }
 }
 
+// Per-tile delay tables for plans with many microphones: the reference
+// delays (the tile's first direction) and, per direction, the window offset
+// clamp(delay - reference + halo, 0, 2 halo); empty direction slots get 0.
+template <bool NEAR>
+__global__ void __launch_bounds__(dmas::kDirsPerTile * dmas::kWaveSize)
+tile_table_kernel(const double *__restrict__ mic, const double *__restrict__ dirs,
+                  const int32_t *__restrict__ tiles, int M, double fs, double c, int halo,
+                  uint16_t *__restrict__ rel, int32_t *__restrict__ dref)
+{
+    constexpr int W = dmas::kDirsPerTile;
+    const int lane = threadIdx.x % dmas::kWaveSize;
+    const int wave = threadIdx.x / dmas::kWaveSize;
+    const int dir = tiles[blockIdx.x * W + wave];
+    const int dir0 = tiles[blockIdx.x * W];
+    uint16_t *row = rel + ((size_t)blockIdx.x * W + wave) * M;
+    for (int i = lane; i < M; i += dmas::kWaveSize) {
+        float f;
+        const int d0 = dmas::steer_whole<NEAR, false>(mic + 3 * i, dirs + 3 * dir0, fs, c, &f);
+        if (wave == 0) dref[(size_t)blockIdx.x * M + i] = d0;
+        int r = 0;
+        if (dir >= 0) {
+            const int dw = dmas::steer_whole<NEAR, false>(mic + 3 * i, dirs + 3 * dir, fs, c, &f);
+            r = min(max(dw - d0 + halo, 0), 2 * halo);
+        }
+        row[i] = (uint16_t)r;
+    }
+}
+
 template <bool NEAR, bool LINEAR>
 __global__ void delay_table_kernel(const double *__restrict__ mic, const double *__restrict__ dirs,
                                    int M, int D, double fs, double c, int32_t *__restrict__ whole,
@@ -138,6 +170,8 @@ void plan_free(dmas_plan_s *p)
     hipFree(p->d_mic);
     hipFree(p->d_dirs);
     hipFree(p->d_tiles);
+    hipFree(p->d_tile_rel);
+    hipFree(p->d_tile_dref);
     hipFree(p->d_taps);
     hipFree(p->d_pulse);
     if (switched) hipSetDevice(cur);
@@ -583,6 +617,27 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         }
         p->halo = 0;
         for (int v : spread) p->halo = std::max(p->halo, v);
+    }
+    // Per-tile delay tables when the delays cannot stay in registers (M > 64)
+    // and the table is of modest size: the kernel then reads offsets instead
+    // of re-evaluating eq. (1) per block of microphones and chunk.
+    const size_t table_bytes = (size_t)p->num_tiles * M * (W * sizeof(uint16_t) + sizeof(int32_t));
+    if (M > dmas::kWaveSize && !p->linear && 2 * p->halo <= UINT16_MAX && table_bytes <= kMaxTileTableBytes &&
+        !std::getenv("DMAS_NO_DELAY_TABLE")) {
+        const size_t n_rel = (size_t)p->num_tiles * W * M, n_dref = (size_t)p->num_tiles * M;
+        e = hipMalloc((void **)&p->d_tile_rel, sizeof(uint16_t) * n_rel);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_tile_dref, sizeof(int32_t) * n_dref);
+        if (e == hipSuccess) {
+            auto kern = p->nearfield ? tile_table_kernel<true> : tile_table_kernel<false>;
+            hipLaunchKernelGGL(kern, dim3(p->num_tiles), dim3(W * dmas::kWaveSize), 0, nullptr, p->d_mic, p->d_dirs,
+                               p->d_tiles, M, p->fs, p->c, p->halo, p->d_tile_rel, p->d_tile_dref);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        }
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_fail(e, "tile delay table");
+        }
     }
 
     // ---- LDS layout: mic_block x row windows, reference delays, envelope rings ----

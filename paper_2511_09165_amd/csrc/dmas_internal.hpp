@@ -21,6 +21,9 @@ struct KernelParams {
     const double *mic;        // M x 3, device
     const double *dirs;       // D x 3, device
     const int32_t *tile_dirs; // num_tiles x dirs_per_tile direction indices (-1 = empty), device
+    const uint16_t *tile_rel; // optional, num_tiles x dirs_per_tile x M: window offset of each
+                              // direction's delay, clamp(delay - reference + halo, 0, 2 halo)
+    const int32_t *tile_dref; // optional, num_tiles x M: reference (first direction) delays
     const float *taps;        // fir_len envelope taps, device
     int32_t M, T, D;
     int32_t order;            // n

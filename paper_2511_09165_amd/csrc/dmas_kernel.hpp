@@ -191,7 +191,18 @@ __device__ __forceinline__ void stage_row_roots(float2 *__restrict__ dst, const 
     if (base >= 0 && base + row <= T) {
         const float2 *src = plane + chan + (size_t)base + lane;
         float2 *d = dst + lane;
-        for (int r = 0; r < row - lane; r += kWaveSize) d[r] = src[r];
+        const int full = row / kWaveSize;   // whole wave-wide steps (wave-uniform)
+        int r = 0;
+        for (; r + 4 <= full; r += 4) {
+            const float2 a0 = src[(r + 0) * kWaveSize], a1 = src[(r + 1) * kWaveSize];
+            const float2 a2 = src[(r + 2) * kWaveSize], a3 = src[(r + 3) * kWaveSize];
+            d[(r + 0) * kWaveSize] = a0;
+            d[(r + 1) * kWaveSize] = a1;
+            d[(r + 2) * kWaveSize] = a2;
+            d[(r + 3) * kWaveSize] = a3;
+        }
+        for (; r < full; ++r) d[r * kWaveSize] = src[r * kWaveSize];
+        if (lane < row - full * kWaveSize) d[full * kWaveSize] = src[full * kWaveSize];
     } else {
         for (int r = lane; r < row; r += kWaveSize) {
             const int t = base + r;
@@ -394,19 +405,33 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int nblocks = (p.M + p.mic_block - 1) / p.mic_block;
     const int two_halo = 2 * p.halo;
 
-    // Steering delays. With M <= 64 lane i of every wave computes its
-    // direction's delay for microphone i once, and wave 0 (the tile's
-    // reference direction) publishes its delays in LDS for the staging step.
-    // With more microphones the same is done per block of microphones (lane i
-    // holding microphone i of the block), once per block and chunk. After a
-    // barrier each lane turns (delay - reference delay) into its LDS offset.
+    // Steering delays, three ways:
+    //  * M <= 64: lane i of every wave computes its direction's delay for
+    //    microphone i once, and wave 0 (the tile's reference direction)
+    //    publishes its delays in LDS for the staging step;
+    //  * a plan-time table (more microphones, whole-sample delays): each lane
+    //    reads its microphone's window offset and the staging step the
+    //    reference delay, per block of microphones;
+    //  * otherwise the first way per block of microphones (lane i holding
+    //    microphone i of the block), once per block and chunk.
+    // After a barrier each lane turns (delay - reference delay) into its LDS
+    // offset.
     const bool all_mics = p.M <= kWaveSize;
+    const bool table = !all_mics && p.tile_rel != nullptr;
+    const uint16_t *__restrict__ rel_row = table ? p.tile_rel + ((size_t)tile * W + wave) * p.M : nullptr;
+    const int32_t *__restrict__ dref_row = table ? p.tile_dref + (size_t)tile * p.M : nullptr;
     int mydw = 0;
     int myoff = 0;
+    int myrel = 0;            // table offset of microphone `lane` of the next block
     float myfrac = 0.0f;      // fraction of mydw's microphone (linear delays)
     float myfrac_blk = 0.0f;  // fraction of microphone `lane` of the current block
     auto block_geometry = [&](int blk) {
         const int mic = blk * p.mic_block + lane;
+        if (table) {
+            // issued before the barrier so the load overlaps the wait and staging
+            if (lane < p.mic_block && mic < p.M) myrel = rel_row[mic];
+            return;
+        }
         const int nlanes = all_mics ? p.M : p.mic_block;
         if (lane < nlanes) {
             if (mic < p.M) {
@@ -418,7 +443,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         }
     };
     // Reference delay of microphone i of block blk.
-    auto dref_of = [&](int blk, int i) { return dref_lds[all_mics ? blk * p.mic_block + i : i]; };
+    auto dref_of = [&](int blk, int i) {
+        return table ? dref_row[blk * p.mic_block + i] : dref_lds[all_mics ? blk * p.mic_block + i : i];
+    };
     auto block_offsets = [&](int blk) {
         const int mic = blk * p.mic_block + lane;
         int dw = mydw;
@@ -432,7 +459,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         }
         if (lane < p.mic_block) {
             int rel = 0;
-            if (mic < p.M)
+            if (table)
+                rel = mic < p.M ? myrel : 0;   // clamped to [0, 2 halo] when the table was built
+            else if (mic < p.M)
                 rel = min(max(dw - dref_of(blk, lane) + p.halo, 0), two_halo);  // the measured halo keeps this in range
             myoff = lane * p.row + rel;
             if constexpr (LINEAR) myfrac_blk = fr;

@@ -31,6 +31,8 @@ struct dmas_plan_s {
     double *d_mic = nullptr;
     double *d_dirs = nullptr;
     int32_t *d_tiles = nullptr;
+    uint16_t *d_tile_rel = nullptr;   // per-tile delay tables (M > 64, whole-sample delays), or null
+    int32_t *d_tile_dref = nullptr;
     float *d_taps = nullptr;
     int env_decim = 1;
     int mf_len = 0;
@@ -63,6 +65,8 @@ inline KernelParams make_params(const dmas_plan_s *plan, const void *d_x, const 
     kp.mic = plan->d_mic;
     kp.dirs = plan->d_dirs;
     kp.tile_dirs = plan->d_tiles;
+    kp.tile_rel = plan->d_tile_rel;
+    kp.tile_dref = plan->d_tile_dref;
     kp.taps = plan->d_taps;
     kp.M = plan->M;
     kp.T = plan->T;

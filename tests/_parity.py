@@ -78,3 +78,32 @@ def check_t3(env: np.ndarray, env_ref: np.ndarray, floor_db: float = -60.0, tol_
     worst = float(db.max())
     assert worst <= tol_db, f"T3 envelope deviation {worst:.4f} dB > {tol_db} dB"
     return worst
+
+
+def delay_rounding_ties(fs: float = 450e3, c: float = 343.0, count: int = 24, span: int = 3000):
+    """Mic x-coordinates (metres, far-field direction (1, 0, 0)) whose whole-sample delay
+    floor(fs * tau + 1/2), tau = -x / c, evaluated as separately rounded IEEE double
+    operations differs from the value a fused multiply-add fs * tau + 1/2 would give.
+    Returns [(x, unfused, fused)]; used to check that delays follow the unfused sequence."""
+    import math
+    from fractions import Fraction
+    out = []
+    half = Fraction(1, 2)
+    for k in range(-60, 60):
+        x0 = (k + 0.5) * c / fs
+        cand = [x0]
+        for direction in (-math.inf, math.inf):
+            v = x0
+            for _ in range(span):
+                v = float(np.nextafter(v, direction))
+                cand.append(v)
+        for x in cand:
+            tau = -x / c
+            unfused = math.floor(fs * tau + 0.5)
+            fused = math.floor(Fraction(fs) * Fraction(tau) + half)
+            if unfused != fused:
+                out.append((x, unfused, fused))
+                break
+        if len(out) >= count:
+            break
+    return out

@@ -90,6 +90,27 @@ def test_steering_delays_bit_exact(case):
         assert np.all(frac == 0)
 
 
+def test_delays_at_rounding_ties():
+    """Geometry where fs*tau + 1/2 fused into one FMA would round to the other sample: the delay
+    table and the beamformer's own delays both follow the unfused IEEE sequence of the oracle."""
+    from _parity import delay_rounding_ties
+    ties = delay_rounding_ties()
+    mic = np.array([[x, 0.0, 0.0] for x, _, _ in ties])
+    rng = np.random.default_rng(41)
+    dirs = np.vstack([[1.0, 0.0, 0.0], synth.unit_vectors(rng.uniform(-80, 80, 20), rng.uniform(-20, 20, 20))])
+    f = synth.Frame(name="delay-ties", x=rng.standard_normal((len(ties), 700)), mic_pos=mic, dirs=dirs, fs=450e3, c=343.0,
+                    order=3, use_cf=False, nearfield=False)
+    _say(f"delay ties M={len(ties)}")
+    with _plan(f) as plan:
+        whole, _ = plan.steering_delays()
+        whole = whole.cpu().numpy()
+    d_ref = oracle.delays(f.mic_pos, f.dirs, f.fs, f.c)
+    assert np.array_equal(whole, d_ref.astype(np.int32))
+    assert [int(v) for v in whole[0]] == [u for _, u, _ in ties]
+    # a one-sample slip of any microphone would move this noise image by far more than T1
+    _compare(f, f.x_f32(), check_env=False, t2=False)
+
+
 # ---------------------------------------------------------------------------
 # Whole images at small sizes (several tiles, ragged tails)
 # ---------------------------------------------------------------------------
@@ -118,6 +139,19 @@ def test_microphone_blocks(nearfield):
     f = synth.random_frame(np.random.default_rng(7), 150, 13, 600, 3, nearfield=nearfield)
     _say(f"mic blocks near={nearfield}")
     _compare(f, f.x_f32())
+
+
+@pytest.mark.parametrize("nearfield", [False, True])
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_delay_table_matches_per_block_delays(n, nearfield, monkeypatch):
+    """With M > 64 the plan keeps per-tile delay tables; the images equal, bit for bit, those of a
+    plan that evaluates eq. (1) per microphone block instead (DMAS_NO_DELAY_TABLE)."""
+    f = synth.random_frame(np.random.default_rng(8 + n), 150, 37, 900, n, nearfield=nearfield)
+    _say(f"delay table n={n} near={nearfield}")
+    a = _run(f, f.x_f32(), env=True)
+    monkeypatch.setenv("DMAS_NO_DELAY_TABLE", "1")
+    b = _run(f, f.x_f32(), env=True)
+    assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("M,D,T,n", [(1, 1, 1, 1), (3, 1, 2, 3), (5, 9, 63, 2), (8, 8, 255, 5), (8, 8, 256, 5),

@@ -279,6 +279,21 @@ def test_delay_table_matches_rows():
     np.testing.assert_allclose(y, yb, rtol=1e-11, atol=1e-12)
 
 
+def test_delays_follow_unfused_ieee_sequence():
+    """Eq. (1) rounded to the nearest sample as separately rounded IEEE double operations:
+    tau = -(r . u)/c, f = fs * tau, d = floor(f + 1/2). Geometries where a fused fs*tau + 1/2
+    would land on the other side of an integer pin the oracle to the unfused sequence."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _parity import delay_rounding_ties
+    ties = delay_rounding_ties()
+    assert len(ties) >= 8
+    mic = np.array([[x, 0.0, 0.0] for x, _, _ in ties])
+    d = oracle.delays(mic, np.array([[1.0, 0.0, 0.0]]), 450e3, 343.0)[0]
+    assert [int(v) for v in d] == [u for _, u, _ in ties]
+    assert all(u != fz for _, u, fz in ties)
+
+
 def test_zero_outside_record():
     """Samples steered outside [0, T) are zero: a one-sample record with a large delay sees nothing."""
     x = np.ones((3, 4))
