@@ -646,7 +646,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
     p->row = (p->row + 3) & ~3;
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
-    const size_t ring_bytes = sizeof(float) * (size_t)W * dmas::ring_stride(H);
+    const size_t ring_bytes = sizeof(float) * (size_t)dmas::env_lds_floats(H, W);
     const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
     // Microphones per LDS block: the largest block whose footprint lets three
     // workgroups share a CU (else two, else one). More blocks cost barriers and

@@ -66,12 +66,18 @@ constexpr int kDirsPerTile = 8;
 constexpr int kSamplesPerLane = 4;
 constexpr int kChunk = kWaveSize * kSamplesPerLane;
 
-// Envelope ring of one wave (floats): the |y| value of ring index i sits at
-// ring_pad(H) + i, for i in [0, kChunk + 2H). The pad (4 to 7 floats, zero)
-// puts index 2H on a 16-byte boundary and gives the FIR's lowest 16-byte
-// group read a zero block to land on; the stride keeps rings 16-byte aligned.
-__host__ __device__ constexpr int ring_pad(int H) { return 4 + (4 - (2 * H) % 4) % 4; }
-__host__ __device__ constexpr int ring_stride(int H) { return (ring_pad(H) + kChunk + 2 * H + 3) & ~3; }
+// Envelope LDS of a workgroup (floats), after the windows and reference
+// delays: a taps table of env_taps_len(H) floats (kTapLead zeros, the L =
+// 2H + 1 taps, zeros), then one ring per wave of ring_stride(H) floats. The
+// ring holds |y| for ring index i in [0, kChunk + 2H) at float i + i / 16;
+// the skew keeps the FIR's matrix-operand reads (16 indices 16 apart) on
+// distinct LDS banks. The FIR is a product with K = 2H + 16 in steps of 4.
+constexpr int kTapLead = 20;
+__host__ __device__ constexpr int env_ksteps(int H) { return (2 * H + 16 + 3) / 4; }
+__host__ __device__ constexpr int env_taps_len(int H) { return (kTapLead + 2 * H + 1 + 16 + 3) & ~3; }
+__host__ __device__ constexpr int ring_logical(int H) { return kChunk + 2 * H + 8; }
+__host__ __device__ constexpr int ring_stride(int H) { return (ring_logical(H) + ring_logical(H) / 16 + 1 + 3) & ~3; }
+__host__ __device__ constexpr int env_lds_floats(int H, int waves) { return env_taps_len(H) + waves * ring_stride(H); }
 // Envelope taps on the device: fir_len taps, zero-padded to a multiple of 4.
 __host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; }
 

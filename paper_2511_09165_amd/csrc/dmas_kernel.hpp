@@ -251,6 +251,7 @@ template <int ACC, typename T>
 __device__ __forceinline__ void acc_add(T &sum, float &comp, T term)
 {
     if constexpr (ACC == kAccKahan) {
+#pragma clang fp contract(off)
         const T y = term - comp;
         const T t = sum + y;
         comp = (t - sum) - y;
@@ -260,30 +261,56 @@ __device__ __forceinline__ void acc_add(T &sum, float &comp, T term)
     }
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T mul_rounded(T a, T b)
+{
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+// sum += a * b: one fused multiply-add for plain sums; for Kahan sums the
+// product is rounded first and then added with compensation.
+template <int ACC, typename T>
+__device__ __forceinline__ void acc_fma(T &sum, float &comp, T a, T b)
+{
+    if constexpr (ACC == kAccKahan) acc_add<ACC>(sum, comp, mul_rounded(a, b));
+    else sum = fma_t(a, b, sum);
+}
+
+// Factors of s^k used to form it: s^k = s^fa(k) * s^fb(k).
+__host__ __device__ constexpr int pow_fa(int k) { return (k & 1) ? k - 1 : k / 2; }
+__host__ __device__ constexpr int pow_fb(int k) { return (k & 1) ? 1 : k / 2; }
+
 // Adds one microphone's terms given its signed root sv = sgn(x)|x|^(1/N) and
-// its sample xv.
+// its sample xv. The operations are written out rather than left to the
+// compiler's contraction, so every kernel that calls this rounds alike:
+// P_1 += s; P_k = fma(s^fa, s^fb, P_k) for 2 <= k < N, with the powers that
+// later terms need formed by a rounded multiply; P_N += x (odd N) or |x|
+// (s^N is x or |x|); with CF, B = fma(x, x, B) and, for even N, A += x.
 template <int N, bool CF, int ACC>
 __device__ __forceinline__ void accumulate_root(Acc<N, CF, ACC> &acc, float sv, float xv)
 {
     using T = AccType<ACC>;
     constexpr bool KAHAN = ACC == kAccKahan;
+    const T x = T(xv);
     if constexpr (N == 1) {
-        const T x = T(xv);
         acc_add<ACC>(acc.p[1], acc.cp[KAHAN ? 1 : 0], x);
-        if constexpr (CF) acc_add<ACC>(acc.b, acc.cb, x * x);
-        return;
     } else {
-        T pw[N];                       // pw[k] = s^k, k = 1..N-1
+        T pw[N];                       // pw[k] = s^k (those a later term uses)
         pw[1] = T(sv);
-        if constexpr (N >= 3) pw[2] = pw[1] * pw[1];
+        acc_add<ACC>(acc.p[1], acc.cp[KAHAN ? 1 : 0], pw[1]);
 #pragma unroll
-        for (int k = 3; k < N; ++k) pw[k] = (k & 1) ? pw[k - 1] * pw[1] : pw[k / 2] * pw[k / 2];
-#pragma unroll
-        for (int k = 1; k < N; ++k) acc_add<ACC>(acc.p[k], acc.cp[KAHAN ? k : 0], pw[k]);
-        acc_add<ACC>(acc.p[N], acc.cp[KAHAN ? N : 0], T((N & 1) ? xv : __builtin_fabsf(xv)));
-        if constexpr (CF && !(N & 1)) acc_add<ACC>(acc.a, acc.ca, T(xv));
-        if constexpr (CF) acc_add<ACC>(acc.b, acc.cb, T(xv) * T(xv));
+        for (int k = 2; k < N; ++k) {
+            acc_fma<ACC>(acc.p[k], acc.cp[KAHAN ? k : 0], pw[pow_fa(k)], pw[pow_fb(k)]);
+            pw[k] = mul_rounded(pw[pow_fa(k)], pw[pow_fb(k)]);
+        }
+        acc_add<ACC>(acc.p[N], acc.cp[KAHAN ? N : 0], (N & 1) ? x : T(__builtin_fabsf(xv)));
+        if constexpr (CF && !(N & 1)) acc_add<ACC>(acc.a, acc.ca, x);
     }
+    if constexpr (CF) acc_fma<ACC>(acc.b, acc.cb, x, x);
 }
 
 template <int N, bool CF, int ACC>
@@ -385,8 +412,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int H = ENV ? (p.fir_len - 1) / 2 : 0;
     Elem *xwin = reinterpret_cast<Elem *>(smem);                   // mic_block x row
     int *dref_lds = reinterpret_cast<int *>(xwin + p.mic_block * p.row);  // kMaxMicBlock
-    float *ring_buf = reinterpret_cast<float *>(dref_lds + kMaxMicBlock) + wave * ring_stride(H);
-    float *ring = ring_buf + ring_pad(H);                          // ring[i], i in [0, C + 2H)
+    float *tap_lds = reinterpret_cast<float *>(dref_lds + kMaxMicBlock);     // env_taps_len(H)
+    float *ring = tap_lds + env_taps_len(H) + wave * ring_stride(H);         // |y| of index i at i + i/16
 
     const int dir = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W + wave]);
     const int dir0 = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W]);
@@ -473,7 +500,12 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 
     if (all_mics) block_geometry(0);
     if constexpr (ENV) {
-        for (int i = lane; i < ring_pad(H) + 2 * H; i += kWaveSize) ring_buf[i] = 0.0f;
+        for (int i = lane; i < ring_stride(H); i += kWaveSize) ring[i] = 0.0f;
+        for (int j = threadIdx.x; j < env_taps_len(H); j += W * kWaveSize) {
+            const int k = j - kTapLead;
+            tap_lds[j] = (k >= 0 && k < p.fir_len) ? taps[k] : 0.0f;
+        }
+        // the first block's barrier makes the taps table visible before any epilogue
     }
 
     for (int ch = 0; ch < nchunks; ++ch) {
@@ -556,55 +588,38 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
                 const float y = finish_pixel<N, CF, ACC>(acc[j], p);
-                ring[2 * H + lane + kWaveSize * j] = (t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
+                const int ri = 2 * H + lane + kWaveSize * j;
+                ring[ri + (ri >> 4)] = (t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             // env[t] for t = tc - H + o, o in [0, C): sum_k h[k] |y[t + H - k]|
-            //   = sum_k h[k] ring[2H + o - k].
-            // Lane l owns o = 4l + j, j < 4. Taps go in groups of 4: group g
-            // needs ring[2H + 4l - 4g - 3 .. 2H + 4l - 4g + 3], i.e. the 16-byte
-            // block `cur` (ring[2H + 4(l-g) .. +3]) and the block below it, so
-            // each group costs one 16-byte LDS read and 16 FMAs. Taps past
-            // fir_len are zero; the blocks they meet below the ring are the
-            // zeroed pad.
+            //   = sum_k h[k] r[2H + o - k], r = the ring.
+            // With o = 16a + b (a, b < 16) this is the 16 x 16 matrix product
+            //   E[a][b] = sum_m R[a][m] G[m][b],  R[a][m] = r[16a + m],
+            //   G[m][b] = h[b + 2H - m] (zero outside the taps), m < 2H + 16,
+            // done on the matrix cores in FP32, K = 4 per step: lane l holds
+            // R[l % 16][4kk + l / 16] and G[4kk + l / 16][l % 16] and receives
+            // E[4 (l / 16) + v][l % 16], v < 4.
             if (p.env_decim == 1) {
-                const float4 *rb4 = reinterpret_cast<const float4 *>(ring + 2 * H) + lane;
-                const int ngroups = fir_taps_padded(p.fir_len) / 4;
-                float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f, e3 = 0.0f;
-                float4 cur = rb4[0];
-                for (int g = 0; g < ngroups; ++g) {
-                    const float4 lo = rb4[-g - 1];
-                    const float h0 = taps[4 * g], h1 = taps[4 * g + 1], h2 = taps[4 * g + 2], h3 = taps[4 * g + 3];
-                    e0 = __builtin_fmaf(h0, cur.x, e0);
-                    e0 = __builtin_fmaf(h1, lo.w, e0);
-                    e0 = __builtin_fmaf(h2, lo.z, e0);
-                    e0 = __builtin_fmaf(h3, lo.y, e0);
-                    e1 = __builtin_fmaf(h0, cur.y, e1);
-                    e1 = __builtin_fmaf(h1, cur.x, e1);
-                    e1 = __builtin_fmaf(h2, lo.w, e1);
-                    e1 = __builtin_fmaf(h3, lo.z, e1);
-                    e2 = __builtin_fmaf(h0, cur.z, e2);
-                    e2 = __builtin_fmaf(h1, cur.y, e2);
-                    e2 = __builtin_fmaf(h2, cur.x, e2);
-                    e2 = __builtin_fmaf(h3, lo.w, e2);
-                    e3 = __builtin_fmaf(h0, cur.w, e3);
-                    e3 = __builtin_fmaf(h1, cur.z, e3);
-                    e3 = __builtin_fmaf(h2, cur.y, e3);
-                    e3 = __builtin_fmaf(h3, cur.x, e3);
-                    cur = lo;
+                typedef float v4f __attribute__((ext_vector_type(4)));
+                const int g = lane >> 4, c = lane & 15;
+                const float *ra = ring + 17 * c + g;                  // r[16c + g], skewed
+                const float *hb = tap_lds + kTapLead + c + 2 * H - g; // h[c + 2H - g]
+                const int ks = env_ksteps(H);
+                v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
+                int kk = 0;
+                for (; kk + 1 < ks; kk += 2) {
+                    e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[4 * kk + (kk >> 2)], hb[-4 * kk], e0, 0, 0, 0);
+                    e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[4 * (kk + 1) + ((kk + 1) >> 2)], hb[-4 * (kk + 1)],
+                                                              e1, 0, 0, 0);
                 }
-                const int t0 = tc - H + 4 * lane;   // a multiple of 4 (tc - H is one of 32)
-                float *dst = p.out + orow + t0;
-                if (t0 >= g0 && t0 + 3 < g1 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-                    typedef float v4f __attribute__((ext_vector_type(4)));
-                    const v4f v = {e0, e1, e2, e3};
-                    __builtin_nontemporal_store(v, reinterpret_cast<v4f *>(dst));
-                } else {
-                    const float ev[4] = {e0, e1, e2, e3};
+                if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[4 * kk + (kk >> 2)], hb[-4 * kk], e0, 0, 0, 0);
+                const v4f e = e0 + e1;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (t0 + j >= g0 && t0 + j < g1) __builtin_nontemporal_store(ev[j], dst + j);
+                for (int v = 0; v < 4; ++v) {
+                    const int t = tc - H + 64 * g + 16 * v + c;
+                    if (t >= g0 && t < g1) __builtin_nontemporal_store(e[v], p.out + orow + t);
                 }
             } else {
                 // Decimated envelope: only the outputs at t = j * env_decim, each
@@ -617,9 +632,12 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                     const int j0 = (lo + dec - 1) / dec;   // lo >= 0
                     const int j1 = (hi + dec - 1) / dec;
                     for (int jo = j0 + lane; jo < j1; jo += kWaveSize) {
-                        const float *src = ring + 2 * H + (jo * dec - t_lo);
+                        const int i0 = 2 * H + (jo * dec - t_lo);
                         float e = 0.0f;
-                        for (int k = 0; k < p.fir_len; ++k) e = __builtin_fmaf(taps[k], src[-k], e);
+                        for (int k = 0; k < p.fir_len; ++k) {
+                            const int ri = i0 - k;
+                            e = __builtin_fmaf(taps[k], ring[ri + (ri >> 4)], e);
+                        }
                         __builtin_nontemporal_store(e, p.out + orow + jo);
                     }
                 }
@@ -627,7 +645,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             // keep the last 2H values of |y| for the next chunk (2H <= C: no overlap)
-            for (int i = lane; i < 2 * H; i += kWaveSize) ring[i] = ring[C + i];
+            for (int i = lane; i < 2 * H; i += kWaveSize) ring[i + (i >> 4)] = ring[C + i + ((C + i) >> 4)];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
