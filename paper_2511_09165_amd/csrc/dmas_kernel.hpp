@@ -449,14 +449,18 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int32_t *__restrict__ dref_row = table ? p.tile_dref + (size_t)tile * p.M : nullptr;
     int mydw = 0;
     int myoff = 0;
-    int myrel = 0;            // table offset of microphone `lane` of the next block
+    int myrel = 0;            // table offset of microphone `lane` of the block (table mode)
+    int mydref = 0;           // reference delay of microphone `lane` of the block (table mode)
     float myfrac = 0.0f;      // fraction of mydw's microphone (linear delays)
     float myfrac_blk = 0.0f;  // fraction of microphone `lane` of the current block
     auto block_geometry = [&](int blk) {
         const int mic = blk * p.mic_block + lane;
         if (table) {
-            // issued before the barrier so the load overlaps the wait and staging
-            if (lane < p.mic_block && mic < p.M) myrel = rel_row[mic];
+            // issued before the barrier so the loads overlap the wait
+            if (lane < p.mic_block && mic < p.M) {
+                myrel = rel_row[mic];
+                mydref = dref_row[mic];
+            }
             return;
         }
         const int nlanes = all_mics ? p.M : p.mic_block;
@@ -469,9 +473,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             }
         }
     };
-    // Reference delay of microphone i of block blk.
+    // Reference delay of microphone i (wave-uniform) of block blk, for staging.
     auto dref_of = [&](int blk, int i) {
-        return table ? dref_row[blk * p.mic_block + i] : dref_lds[all_mics ? blk * p.mic_block + i : i];
+        return table ? __builtin_amdgcn_readlane(mydref, i) : dref_lds[all_mics ? blk * p.mic_block + i : i];
     };
     auto block_offsets = [&](int blk) {
         const int mic = blk * p.mic_block + lane;
@@ -489,7 +493,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             if (table)
                 rel = mic < p.M ? myrel : 0;   // clamped to [0, 2 halo] when the table was built
             else if (mic < p.M)
-                rel = min(max(dw - dref_of(blk, lane) + p.halo, 0), two_halo);  // the measured halo keeps this in range
+                rel = min(max(dw - dref_lds[all_mics ? mic : lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
             myoff = lane * p.row + rel;
             if constexpr (LINEAR) myfrac_blk = fr;
         }
