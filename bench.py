@@ -94,20 +94,28 @@ def measured_traffic(workload_key: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(frame, fir_len: int, stride: int = 4) -> dict:
-    """Time the FP64 oracle on every ``stride``-th direction of the same frame (rows + envelope)."""
+def cpu_baseline(frame, fir_len: int, min_seconds: float = 10.0, max_seconds: float = 30.0) -> dict:
+    """Time the FP64 oracle (rows + envelope) on the same frame, whole frames repeated until at
+    least ``min_seconds`` of wall time have passed (a frame is dropped from the count if it would
+    push the total past ``max_seconds``)."""
     import oracle
     taps = oracle.lowpass_taps(fir_len, 5000.0, frame.fs)
-    rows = list(range(0, frame.num_dirs, stride))
     x64 = frame.x_f32().astype(np.float64)
-    t0 = time.perf_counter()
-    y = oracle.frame_rows(frame, x=x64, rows=rows)
-    oracle.envelope(y, taps)
-    dt = time.perf_counter() - t0
-    pix = len(rows) * frame.num_samples
-    return {"value": pix / dt, "unit": "direction*samples/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{len(rows)} of {frame.num_dirs} directions (every {stride}th) x {frame.num_samples} "
-                      f"samples, order-5 DMAS+CF+envelope, FP64, {dt:.2f} s wall"}
+    rows = list(range(frame.num_dirs))
+    frames, elapsed = 0, 0.0
+    while elapsed < min_seconds:
+        t0 = time.perf_counter()
+        y = oracle.frame_rows(frame, x=x64, rows=rows)
+        oracle.envelope(y, taps)
+        dt = time.perf_counter() - t0
+        if frames and elapsed + dt > max_seconds:
+            break
+        frames += 1
+        elapsed += dt
+    pix = frames * frame.num_dirs * frame.num_samples
+    return {"value": pix / elapsed, "unit": "direction*samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{frames} whole frames ({frame.num_dirs} directions x {frame.num_samples} samples each), "
+                      f"order-5 DMAS+CF+envelope, FP64, {elapsed:.1f} s wall"}
 
 
 def _timed(launch, steps: int, warmup: int, stream):
@@ -333,7 +341,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=200, help="untimed steps first (clocks settle in ~100 ms)")
-    ap.add_argument("--serving-rates", default="250,500,1000,1500,2000", help="offered frames/s (serving)")
+    ap.add_argument("--serving-rates", default="500,1000,2000,3000,4000", help="offered frames/s (serving)")
     ap.add_argument("--serving-duration", type=float, default=2.0, help="seconds of arrivals per rate (serving)")
     ap.add_argument("--serving-pool", type=int, default=48, help="distinct frames in the serving pool")
     ap.add_argument("--workload", default="erti32", choices=["erti32", "nearfield", "precision", "serving"],
