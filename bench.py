@@ -94,10 +94,21 @@ def measured_traffic(workload_key: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(frame, fir_len: int, min_seconds: float = 10.0, max_seconds: float = 30.0) -> dict:
-    """Time the FP64 oracle (rows + envelope) on the same frame, whole frames repeated until at
-    least ``min_seconds`` of wall time have passed (a frame is dropped from the count if it would
-    push the total past ``max_seconds``)."""
+    """Time the FP64 oracle (rows + envelope) on the same frame with all its threads: whole frames
+    repeated until at least ``min_seconds`` of wall time (a frame that would push the total past
+    ``max_seconds`` is not counted); then on one thread over every 64th direction."""
     import oracle
     taps = oracle.lowpass_taps(fir_len, 5000.0, frame.fs)
     x64 = frame.x_f32().astype(np.float64)
@@ -112,10 +123,38 @@ def cpu_baseline(frame, fir_len: int, min_seconds: float = 10.0, max_seconds: fl
             break
         frames += 1
         elapsed += dt
+    threads = oracle.num_threads()
+    sub = rows[::64]
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        y = oracle.frame_rows(frame, x=x64, rows=sub)
+        oracle.envelope(y, taps)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
     pix = frames * frame.num_dirs * frame.num_samples
-    return {"value": pix / elapsed, "unit": "direction*samples/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": pix / elapsed, "unit": "direction*samples/s", "cores": threads, "kind": "oracle",
             "sample": f"{frames} whole frames ({frame.num_dirs} directions x {frame.num_samples} samples each), "
-                      f"order-5 DMAS+CF+envelope, FP64, {elapsed:.1f} s wall"}
+                      f"order-5 DMAS+CF+envelope, FP64, {elapsed:.1f} s wall",
+            "cpu_model": _cpu_model(),
+            "one_thread": {"value": len(sub) * frame.num_samples / dt1, "unit": "direction*samples/s",
+                           "sample": f"every 64th direction ({len(sub)}) x {frame.num_samples} samples, "
+                                     f"{dt1:.1f} s wall"}}
+
+
+def _launch_stats(launch, reps: int, stream) -> dict:
+    """Per-launch device times (HIP events around each launch on the launch stream)."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return {"launches": reps, "median_ms": float(np.median(t)), "mean_ms": float(t.mean()),
+            "p95_ms": float(np.percentile(t, 95)), "min_ms": float(t.min()), "max_ms": float(t.max())}
 
 
 def _timed(launch, steps: int, warmup: int, stream):
@@ -175,15 +214,18 @@ def bench_headline(args) -> dict:
     rec["data"] = "synthetic (seeded eRTIS-like pulse-echo frame)"
     rec["roofline"] = _roofline(launch_slots(M, T, D, n, True, fir_len), pixels, kernel_ms,
                                 measured_traffic(workload_key))
+    # per-launch statistics of the same call, then the RF image and CF off (the paper's Table III ratio)
+    reps = max(5, args.steps // 2)
+    rec["launch_stats"] = _launch_stats(lambda: plan.envelope(x, out=out), reps, stream)
+    extra = {"rf_ms": _timed(lambda: plan.beamform(x, out=out), reps, 2, stream)[1]}
+    with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
+        extra["no_cf_env_ms"] = _timed(lambda: p2.envelope(x, out=out), reps, 2, stream)[1]
+    extra["cf_cost"] = kernel_ms / extra["no_cf_env_ms"] - 1.0
     if args.extra:
-        reps = max(5, args.steps // 2)
-        extra = {"rf_ms": _timed(lambda: plan.beamform(x, out=out), reps, 2, stream)[1]}
-        with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
-            extra["no_cf_env_ms"] = _timed(lambda: p2.envelope(x, out=out), reps, 2, stream)[1]
         with plan_for_frame(frame, fir_len=fir_len, ng_fp64=True) as p3:
             extra["ng_fp64_env_ms"] = _timed(lambda: p3.envelope(x, out=out), reps, 2, stream)[1]
         extra["plan"] = plan.info()
-        rec["extra"] = extra
+    rec["extra"] = extra
     rec["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(frame, fir_len)
     plan.close()
     return rec
@@ -348,7 +390,7 @@ def main(argv=None) -> int:
                     help="erti32: the headline frame (default); nearfield: 1024-mic voxel imaging; "
                          "precision: FP16/BF16 storage, FP64 Newton-Girard and Kahan sums, orders 2-7")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extra", action="store_true", help="also time RF output, CF off and FP64 Newton-Girard")
+    ap.add_argument("--extra", action="store_true", help="also time FP64 Newton-Girard and print the plan")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, --steps times (HBM counter calibration)")
     args = ap.parse_args(argv)

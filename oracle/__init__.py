@@ -38,6 +38,8 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     lib.oracle_delays.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
                                   ctypes.c_double, ctypes.c_double, _i64p]
     lib.oracle_delays_frac.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
@@ -66,6 +68,11 @@ def _ptr(a: np.ndarray, typ=_dp):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for later oracle calls (timing only; results do not depend on it)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def delays(mic_pos, dirs, fs: float, c: float, nearfield: bool = False) -> np.ndarray:

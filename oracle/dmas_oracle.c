@@ -55,6 +55,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads used by later calls (n >= 1); timing only, results do not depend on it. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Steering delay of eq. (1) in samples, before rounding: fs * tau.
  * Far field (v is a unit vector toward the source): a plane wave from v
