@@ -102,21 +102,22 @@ tile_spread_kernel(const double *__restrict__ mic, const double *__restrict__ di
     }
 }
 
-// Per-tile delay tables for plans with many microphones: the reference
-// delays (the tile's first direction) and, per direction, the window offset
-// clamp(delay - reference + halo, 0, 2 halo); empty direction slots get 0.
+// Per-tile delay tables: the reference delays (the tile's first direction)
+// and, per direction and microphone, the LDS element where the kernel finds
+// that direction's window: (mic % mic_block) * row + clamp(delay - reference
+// + halo, 0, 2 halo); empty direction slots get the row start.
 template <bool NEAR>
 __global__ void __launch_bounds__(dmas::kDirsPerTile * dmas::kWaveSize)
 tile_table_kernel(const double *__restrict__ mic, const double *__restrict__ dirs,
-                  const int32_t *__restrict__ tiles, int M, double fs, double c, int halo,
-                  uint16_t *__restrict__ rel, int32_t *__restrict__ dref)
+                  const int32_t *__restrict__ tiles, int M, double fs, double c, int halo, int mic_block,
+                  int row, int32_t *__restrict__ off, int32_t *__restrict__ dref)
 {
     constexpr int W = dmas::kDirsPerTile;
     const int lane = threadIdx.x % dmas::kWaveSize;
     const int wave = threadIdx.x / dmas::kWaveSize;
     const int dir = tiles[blockIdx.x * W + wave];
     const int dir0 = tiles[blockIdx.x * W];
-    uint16_t *row = rel + ((size_t)blockIdx.x * W + wave) * M;
+    int32_t *dst = off + ((size_t)blockIdx.x * W + wave) * M;
     for (int i = lane; i < M; i += dmas::kWaveSize) {
         float f;
         const int d0 = dmas::steer_whole<NEAR, false>(mic + 3 * i, dirs + 3 * dir0, fs, c, &f);
@@ -126,7 +127,7 @@ tile_table_kernel(const double *__restrict__ mic, const double *__restrict__ dir
             const int dw = dmas::steer_whole<NEAR, false>(mic + 3 * i, dirs + 3 * dir, fs, c, &f);
             r = min(max(dw - d0 + halo, 0), 2 * halo);
         }
-        row[i] = (uint16_t)r;
+        dst[i] = (i % mic_block) * row + r;
     }
 }
 
@@ -170,7 +171,7 @@ void plan_free(dmas_plan_s *p)
     hipFree(p->d_mic);
     hipFree(p->d_dirs);
     hipFree(p->d_tiles);
-    hipFree(p->d_tile_rel);
+    hipFree(p->d_tile_off);
     hipFree(p->d_tile_dref);
     hipFree(p->d_taps);
     hipFree(p->d_pulse);
@@ -618,28 +619,6 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         p->halo = 0;
         for (int v : spread) p->halo = std::max(p->halo, v);
     }
-    // Per-tile delay tables when the delays cannot stay in registers (M > 64)
-    // and the table is of modest size: the kernel then reads offsets instead
-    // of re-evaluating eq. (1) per block of microphones and chunk.
-    const size_t table_bytes = (size_t)p->num_tiles * M * (W * sizeof(uint16_t) + sizeof(int32_t));
-    if (M > dmas::kWaveSize && !p->linear && 2 * p->halo <= UINT16_MAX && table_bytes <= kMaxTileTableBytes &&
-        !std::getenv("DMAS_NO_DELAY_TABLE")) {
-        const size_t n_rel = (size_t)p->num_tiles * W * M, n_dref = (size_t)p->num_tiles * M;
-        e = hipMalloc((void **)&p->d_tile_rel, sizeof(uint16_t) * n_rel);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->d_tile_dref, sizeof(int32_t) * n_dref);
-        if (e == hipSuccess) {
-            auto kern = p->nearfield ? tile_table_kernel<true> : tile_table_kernel<false>;
-            hipLaunchKernelGGL(kern, dim3(p->num_tiles), dim3(W * dmas::kWaveSize), 0, nullptr, p->d_mic, p->d_dirs,
-                               p->d_tiles, M, p->fs, p->c, p->halo, p->d_tile_rel, p->d_tile_dref);
-            e = hipGetLastError();
-            if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-        }
-        if (e != hipSuccess) {
-            plan_free(p);
-            return hip_fail(e, "tile delay table");
-        }
-    }
-
     // ---- LDS layout: mic_block x row windows, reference delays, envelope rings ----
     const int C = dmas::kChunk;
     const int H = (L - 1) / 2;
@@ -672,6 +651,29 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->mic_block = mb;
     p->lds_rf = fixed + elem * (size_t)mb * p->row;
     p->lds_env = p->lds_rf + ring_bytes;
+
+    // Per-tile delay tables for whole-sample delays, when of modest size: the
+    // kernel reads window offsets and reference delays through the scalar
+    // cache instead of evaluating eq. (1) on the device and moving the
+    // results between lanes.
+    const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
+    if (!p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE")) {
+        const size_t n_off = (size_t)p->num_tiles * W * M, n_dref = (size_t)p->num_tiles * M;
+        e = hipMalloc((void **)&p->d_tile_off, sizeof(int32_t) * n_off);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_tile_dref, sizeof(int32_t) * n_dref);
+        if (e == hipSuccess) {
+            auto kern = p->nearfield ? tile_table_kernel<true> : tile_table_kernel<false>;
+            hipLaunchKernelGGL(kern, dim3(p->num_tiles), dim3(W * dmas::kWaveSize), 0, nullptr, p->d_mic, p->d_dirs,
+                               p->d_tiles, M, p->fs, p->c, p->halo, p->mic_block, p->row, p->d_tile_off,
+                               p->d_tile_dref);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        }
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_fail(e, "tile delay table");
+        }
+    }
 
     const char *fixed_seg = std::getenv("DMAS_SEGMENT");
     const int seg_override = fixed_seg ? std::atoi(fixed_seg) : 0;

@@ -21,8 +21,9 @@ struct KernelParams {
     const double *mic;        // M x 3, device
     const double *dirs;       // D x 3, device
     const int32_t *tile_dirs; // num_tiles x dirs_per_tile direction indices (-1 = empty), device
-    const uint16_t *tile_rel; // optional, num_tiles x dirs_per_tile x M: window offset of each
-                              // direction's delay, clamp(delay - reference + halo, 0, 2 halo)
+    const int32_t *tile_off;  // optional, num_tiles x dirs_per_tile x M: LDS element where
+                              // each direction's window of each microphone starts,
+                              // (mic % mic_block) * row + clamp(delay - reference + halo, 0, 2 halo)
     const int32_t *tile_dref; // optional, num_tiles x M: reference (first direction) delays
     const float *taps;        // fir_len envelope taps, device
     int32_t M, T, D;
@@ -54,11 +55,18 @@ struct LaunchShape {
     bool cf;
     bool env;
     bool nearfield;
-    bool linear;              // linear fractional-delay interpolation
+    int delay;                // kDelayComputed, kDelayLinear or kDelayTable
     int accumulate;           // power-sum accumulation: 0 FP32, 1 Kahan FP32, 2 FP64
     unsigned grid;            // workgroups
     size_t lds_bytes;         // dynamic LDS
 };
+
+// How a kernel obtains its steering delays: evaluated on the device (whole
+// samples), evaluated with linear interpolation, or from the plan's per-tile
+// tables (whole samples), read through the scalar cache (small tables) or
+// per lane ahead of each microphone block (large tables, which would thrash
+// the scalar cache).
+enum : int { kDelayComputed = 0, kDelayLinear = 1, kDelayTable = 2, kDelayTableLanes = 3 };
 
 // Compile-time tiling shared by host and device: waves (= directions) per
 // workgroup and output samples per lane per chunk.
@@ -82,17 +90,19 @@ __host__ __device__ constexpr int env_lds_floats(int H, int waves) { return env_
 __host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; }
 
 // Batched launch over frames of order n with the given CF / envelope /
-// geometry flags (nearest delays, plain sums); grid = total workgroups.
-hipError_t launch_batch(int order, const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
-                        size_t lds_bytes, hipStream_t stream);
-hipError_t launch_batch_order1(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order2(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order3(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order4(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order5(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order6(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order7(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
-hipError_t launch_batch_order8(const BatchParams &, bool, bool, bool, unsigned, size_t, hipStream_t);
+// geometry flags and whole-sample delay mode (kDelayComputed, kDelayTable or
+// kDelayTableLanes, the same for all frames; plain sums); grid = total
+// workgroups.
+hipError_t launch_batch(int order, const BatchParams &bp, bool cf, bool env, bool nearfield, int delay,
+                        unsigned grid, size_t lds_bytes, hipStream_t stream);
+hipError_t launch_batch_order1(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order2(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order3(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order4(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order5(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order6(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order7(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
+hipError_t launch_batch_order8(const BatchParams &, bool, bool, bool, int, unsigned, size_t, hipStream_t);
 
 // Root plane of a frame: plane[e] = (sgn(x_e) |x_e|^(1/order), x_e) for the
 // count = M * T channel samples of x (storage type dtype), in FP32.

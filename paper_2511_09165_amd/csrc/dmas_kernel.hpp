@@ -324,24 +324,42 @@ __device__ __forceinline__ void accumulate(Acc<N, CF, ACC> &acc, float xv)
 // eqs. (9)-(12); higher orders use the recursive form of the same identities
 // (k e_k = sum_{i=1..k} (-1)^(i-1) e_{k-i} P_i), equivalent to eq. (8).
 // ---------------------------------------------------------------------------
+// The expansions are written as explicit fused multiply-adds (and rounded
+// products), so the rounding does not depend on the compiler's contraction
+// choices in the surrounding kernel.
 template <int N, typename R>
 __device__ __forceinline__ R newton_girard(const R *P)
 {
     if constexpr (N == 1) {
         return P[1];
     } else if constexpr (N == 2) {
-        return R(0.5) * (P[1] * P[1] - P[2]);
+        // (P1^2 - P2) / 2
+        return R(0.5) * fma_t(P[1], P[1], -P[2]);
     } else if constexpr (N == 3) {
-        return R(1.0 / 6.0) * (P[1] * P[1] * P[1] + R(2) * P[3] - R(3) * P[1] * P[2]);
+        // (P1^3 - 3 P1 P2 + 2 P3) / 6
+        const R q = mul_rounded(P[1], P[1]);
+        R t = fma_t(q, P[1], R(2) * P[3]);
+        t = fma_t(mul_rounded(R(-3), P[1]), P[2], t);
+        return R(1.0 / 6.0) * t;
     } else if constexpr (N == 4) {
-        const R q = P[1] * P[1];
-        return R(1.0 / 24.0) *
-               (q * q - R(6) * P[4] + R(3) * P[2] * P[2] - R(6) * P[2] * q + R(8) * P[3] * P[1]);
+        // (P1^4 - 6 P1^2 P2 + 3 P2^2 + 8 P1 P3 - 6 P4) / 24
+        const R q = mul_rounded(P[1], P[1]);
+        R t = fma_t(q, q, R(-6) * P[4]);
+        t = fma_t(mul_rounded(R(3), P[2]), P[2], t);
+        t = fma_t(mul_rounded(R(-6), P[2]), q, t);
+        t = fma_t(mul_rounded(R(8), P[3]), P[1], t);
+        return R(1.0 / 24.0) * t;
     } else if constexpr (N == 5) {
-        const R q = P[1] * P[1];
-        return R(1.0 / 120.0) *
-               (q * q * P[1] - R(10) * P[2] * q * P[1] + R(15) * P[2] * P[2] * P[1] +
-                R(20) * P[3] * q - R(20) * P[3] * P[2] - R(30) * P[1] * P[4] + R(24) * P[5]);
+        // (P1^5 - 10 P1^3 P2 + 15 P1 P2^2 + 20 P1^2 P3 - 20 P2 P3 - 30 P1 P4 + 24 P5) / 120
+        const R q = mul_rounded(P[1], P[1]);
+        const R c = mul_rounded(q, P[1]);
+        R t = fma_t(mul_rounded(q, q), P[1], R(24) * P[5]);
+        t = fma_t(mul_rounded(R(-10), P[2]), c, t);
+        t = fma_t(mul_rounded(mul_rounded(R(15), P[2]), P[2]), P[1], t);
+        t = fma_t(mul_rounded(R(20), P[3]), q, t);
+        t = fma_t(mul_rounded(R(-20), P[3]), P[2], t);
+        t = fma_t(mul_rounded(R(-30), P[1]), P[4], t);
+        return R(1.0 / 120.0) * t;
     } else {
         R e[N + 1];
         e[0] = R(1);
@@ -349,10 +367,7 @@ __device__ __forceinline__ R newton_girard(const R *P)
         for (int k = 1; k <= N; ++k) {
             R s = R(0);
 #pragma unroll
-            for (int i = 1; i <= k; ++i) {
-                const R term = e[k - i] * P[i];
-                s = (i & 1) ? s + term : s - term;
-            }
+            for (int i = 1; i <= k; ++i) s = fma_t((i & 1) ? e[k - i] : -e[k - i], P[i], s);
             e[k] = s * (R(1) / R(k));
         }
         return e[N];
@@ -395,10 +410,13 @@ __device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const 
 // the frame described by p. Shared by the single-frame and the multi-frame
 // (batched) kernels, so a pixel's arithmetic does not depend on how it was
 // launched.
-template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, int ACC>
+template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
 __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile, const int seg,
                                           float *__restrict__ smem)
 {
+    constexpr bool LINEAR = DM == kDelayLinear;
+    constexpr bool TAB = DM == kDelayTable;          // tables through the scalar cache
+    constexpr bool TAB_LANES = DM == kDelayTableLanes; // tables loaded per lane
     constexpr int W = kDirsPerTile;
     constexpr int K = kSamplesPerLane;
     constexpr int C = kChunk;
@@ -433,33 +451,42 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int two_halo = 2 * p.halo;
 
     // Steering delays, three ways:
-    //  * M <= 64: lane i of every wave computes its direction's delay for
-    //    microphone i once, and wave 0 (the tile's reference direction)
-    //    publishes its delays in LDS for the staging step;
-    //  * a plan-time table (more microphones, whole-sample delays): each lane
-    //    reads its microphone's window offset and the staging step the
-    //    reference delay, per block of microphones;
-    //  * otherwise the first way per block of microphones (lane i holding
+    //  * plan-time tables (whole-sample delays): window offsets per (tile,
+    //    direction, microphone) and reference delays per (tile, microphone),
+    //    read through the scalar cache (constant address space: the tables
+    //    do not change while a kernel runs), so the per-microphone LDS
+    //    address of the hot loop costs one vector add;
+    //  * M <= 64 without tables (linear delays): lane i of every wave computes
+    //    its direction's delay for microphone i once, and wave 0 (the tile's
+    //    reference direction) publishes its delays in LDS for the staging step;
+    //  * otherwise the same per block of microphones (lane i holding
     //    microphone i of the block), once per block and chunk.
-    // After a barrier each lane turns (delay - reference delay) into its LDS
-    // offset.
-    const bool all_mics = p.M <= kWaveSize;
-    const bool table = !all_mics && p.tile_rel != nullptr;
-    const uint16_t *__restrict__ rel_row = table ? p.tile_rel + ((size_t)tile * W + wave) * p.M : nullptr;
-    const int32_t *__restrict__ dref_row = table ? p.tile_dref + (size_t)tile * p.M : nullptr;
+    // Without tables, after a barrier each lane turns (delay - reference
+    // delay) into its LDS offset.
+    typedef const __attribute__((address_space(4))) int32_t const_i32;
+    constexpr bool table = TAB;   // p.tile_off and p.tile_dref are set (also with TAB_LANES)
+    const bool all_mics = !table && !TAB_LANES && p.M <= kWaveSize;
+    const_i32 *off_row = table ? reinterpret_cast<const_i32 *>(
+                                     reinterpret_cast<uintptr_t>(p.tile_off + ((size_t)tile * W + wave) * p.M))
+                               : nullptr;
+    const_i32 *dref_row = table ? reinterpret_cast<const_i32 *>(
+                                      reinterpret_cast<uintptr_t>(p.tile_dref + (size_t)tile * p.M))
+                                : nullptr;
+    const int32_t *off_lanes = TAB_LANES ? p.tile_off + ((size_t)tile * W + wave) * p.M : nullptr;
+    const int32_t *dref_lanes = TAB_LANES ? p.tile_dref + (size_t)tile * p.M : nullptr;
+    int mydref = 0;           // reference delay of microphone `lane` of the block (TAB_LANES)
     int mydw = 0;
     int myoff = 0;
-    int myrel = 0;            // table offset of microphone `lane` of the block (table mode)
-    int mydref = 0;           // reference delay of microphone `lane` of the block (table mode)
     float myfrac = 0.0f;      // fraction of mydw's microphone (linear delays)
     float myfrac_blk = 0.0f;  // fraction of microphone `lane` of the current block
     auto block_geometry = [&](int blk) {
+        if (table) return;
         const int mic = blk * p.mic_block + lane;
-        if (table) {
-            // issued before the barrier so the loads overlap the wait
+        if constexpr (TAB_LANES) {
+            // issued before the block's barrier so the loads overlap the wait
             if (lane < p.mic_block && mic < p.M) {
-                myrel = rel_row[mic];
-                mydref = dref_row[mic];
+                myoff = off_lanes[mic];
+                mydref = dref_lanes[mic];
             }
             return;
         }
@@ -475,9 +502,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     };
     // Reference delay of microphone i (wave-uniform) of block blk, for staging.
     auto dref_of = [&](int blk, int i) {
-        return table ? __builtin_amdgcn_readlane(mydref, i) : dref_lds[all_mics ? blk * p.mic_block + i : i];
+        if constexpr (TAB_LANES) return __builtin_amdgcn_readlane(mydref, i);
+        return table ? dref_row[blk * p.mic_block + i] : dref_lds[all_mics ? blk * p.mic_block + i : i];
     };
     auto block_offsets = [&](int blk) {
+        if (table || TAB_LANES) return;
         const int mic = blk * p.mic_block + lane;
         int dw = mydw;
         float fr = myfrac;
@@ -490,9 +519,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         }
         if (lane < p.mic_block) {
             int rel = 0;
-            if (table)
-                rel = mic < p.M ? myrel : 0;   // clamped to [0, 2 halo] when the table was built
-            else if (mic < p.M)
+            if (mic < p.M)
                 rel = min(max(dw - dref_lds[all_mics ? mic : lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
             myoff = lane * p.row + rel;
             if constexpr (LINEAR) myfrac_blk = fr;
@@ -544,9 +571,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             // ---- hot loop: delayed samples -> roots -> power sums ----
             if (active) {
                 const int nm = min(p.mic_block, p.M - blk * p.mic_block);
-#pragma unroll 2
-                for (int i = 0; i < nm; ++i) {
-                    const int off = __builtin_amdgcn_readlane(myoff, i);
+                // microphone i of the block: its window starts at LDS element off
+                auto mic_step = [&](int i, int off) {
                     const Elem *src = xwin + off + lane;
                     if constexpr (ROOTS) {
                         float2 v[K];
@@ -573,6 +599,18 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 #pragma unroll
                         for (int j = 0; j < K; ++j) accumulate<N, CF, ACC>(acc[j], v[j]);
                     }
+                };
+                if (table) {
+                    // the next microphone's offset is loaded while this one is summed
+                    const_i32 *ob = off_row + blk * p.mic_block;
+                    int o_next = ob[0];
+                    for (int i = 0; i < nm; ++i) {
+                        const int o = o_next;
+                        if (i + 1 < nm) o_next = ob[i + 1];
+                        mic_step(i, o);
+                    }
+                } else {
+                    for (int i = 0; i < nm; ++i) mic_step(i, __builtin_amdgcn_readlane(myoff, i));
                 }
             }
         }
@@ -668,18 +706,18 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 // XCDs, so every XCD's L2 reads the whole root plane once per launch (8 x
 // 4 MiB for the eRTIS-like frame); giving each XCD a contiguous range of
 // segments instead cut those reads to 10 MB but measured 4-5 % slower.
-template <int N, bool CF, bool ENV, bool NEAR, bool LINEAR, int ACC>
+template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
 __global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
 dmas_kernel(const KernelParams p)
 {
     extern __shared__ float smem[];
-    dmas_body<N, CF, ENV, NEAR, LINEAR, ACC>(p, blockIdx.x % p.num_tiles, blockIdx.x / p.num_tiles, smem);
+    dmas_body<N, CF, ENV, NEAR, DM, ACC>(p, blockIdx.x % p.num_tiles, blockIdx.x / p.num_tiles, smem);
 }
 
 // Multi-frame kernel for the serving runtime: the batch lists the frames'
 // parameters (all of order N) and the first workgroup index of each frame
 // (ascending); each workgroup finds its frame by binary search.
-template <int N, bool CF, bool ENV, bool NEAR>
+template <int N, bool CF, bool ENV, bool NEAR, int DM>
 __global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
 dmas_batch_kernel(const BatchParams bp)
 {
@@ -693,7 +731,7 @@ dmas_batch_kernel(const BatchParams bp)
     }
     const KernelParams p = bp.frames[lo];
     const int local = b - bp.starts[lo];
-    dmas_body<N, CF, ENV, NEAR, false, kAccF32>(p, local % p.num_tiles, local / p.num_tiles, smem);
+    dmas_body<N, CF, ENV, NEAR, DM, kAccF32>(p, local % p.num_tiles, local / p.num_tiles, smem);
 }
 
 // Dynamic LDS above 64 KiB must be allowed per kernel; the allowed size only
@@ -703,7 +741,7 @@ dmas_batch_kernel(const BatchParams bp)
 // single-frame instantiation has.
 constexpr int kBatchSlot = -1;
 
-template <int N, bool CF, bool ENV, bool NEAR, bool LIN, int ACC>
+template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
 std::atomic<size_t> &lds_limit_slot()
 {
     static std::atomic<size_t> allowed{64 * 1024};
@@ -722,77 +760,92 @@ inline hipError_t raise_lds_limit(const void *fn, size_t lds, std::atomic<size_t
 }
 
 // Host-side launcher for one order: picks the instantiation for the flags.
-// Instantiated: every (CF, envelope, geometry) with nearest delays; linear
-// delays with CF; Kahan and FP64 accumulation for the far field with CF.
-template <int N, bool CF, bool ENV, bool NEAR, bool LIN, int ACC>
+// Instantiated: every (CF, envelope, geometry) with whole-sample delays from
+// tables or computed on the device; linear delays with CF; Kahan and FP64
+// accumulation for the far field with CF.
+template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
 hipError_t launch_one(const KernelParams &p, const LaunchShape &s, hipStream_t stream)
 {
-    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, ACC>;
-    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), s.lds_bytes, lds_limit_slot<N, CF, ENV, NEAR, LIN, ACC>());
+    auto fn = dmas_kernel<N, CF, ENV, NEAR, DM, ACC>;
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), s.lds_bytes, lds_limit_slot<N, CF, ENV, NEAR, DM, ACC>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(s.grid), dim3(kDirsPerTile * kWaveSize), s.lds_bytes, stream, p);
     return hipGetLastError();
 }
 
 // Resident workgroups per CU for this instantiation and LDS size.
-template <int N, bool CF, bool ENV, bool NEAR, bool LIN, int ACC>
+template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
 hipError_t occupancy_one(const LaunchShape &s, int *blocks)
 {
-    auto fn = dmas_kernel<N, CF, ENV, NEAR, LIN, ACC>;
+    auto fn = dmas_kernel<N, CF, ENV, NEAR, DM, ACC>;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(fn),
                                                         kDirsPerTile * kWaveSize, s.lds_bytes);
 }
 
-template <int N, bool CF, bool ENV, bool NEAR>
+template <int N, bool CF, bool ENV, bool NEAR, int DM>
 hipError_t launch_batch_one(const BatchParams &bp, unsigned grid, size_t lds, hipStream_t stream)
 {
-    auto fn = dmas_batch_kernel<N, CF, ENV, NEAR>;
-    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), lds, lds_limit_slot<N, CF, ENV, NEAR, true, kBatchSlot>());
+    auto fn = dmas_batch_kernel<N, CF, ENV, NEAR, DM>;
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), lds, lds_limit_slot<N, CF, ENV, NEAR, DM, kBatchSlot>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kDirsPerTile * kWaveSize), lds, stream, bp);
     return hipGetLastError();
 }
 
-template <int N>
-hipError_t launch_batch_order(const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
-                              size_t lds, hipStream_t stream)
+template <int N, int DM>
+hipError_t launch_batch_dm(const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid, size_t lds,
+                           hipStream_t stream)
 {
     if (cf) {
-        if (env) return nearfield ? launch_batch_one<N, true, true, true>(bp, grid, lds, stream)
-                                  : launch_batch_one<N, true, true, false>(bp, grid, lds, stream);
-        return nearfield ? launch_batch_one<N, true, false, true>(bp, grid, lds, stream)
-                         : launch_batch_one<N, true, false, false>(bp, grid, lds, stream);
+        if (env) return nearfield ? launch_batch_one<N, true, true, true, DM>(bp, grid, lds, stream)
+                                  : launch_batch_one<N, true, true, false, DM>(bp, grid, lds, stream);
+        return nearfield ? launch_batch_one<N, true, false, true, DM>(bp, grid, lds, stream)
+                         : launch_batch_one<N, true, false, false, DM>(bp, grid, lds, stream);
     }
-    if (env) return nearfield ? launch_batch_one<N, false, true, true>(bp, grid, lds, stream)
-                              : launch_batch_one<N, false, true, false>(bp, grid, lds, stream);
-    return nearfield ? launch_batch_one<N, false, false, true>(bp, grid, lds, stream)
-                     : launch_batch_one<N, false, false, false>(bp, grid, lds, stream);
+    if (env) return nearfield ? launch_batch_one<N, false, true, true, DM>(bp, grid, lds, stream)
+                              : launch_batch_one<N, false, true, false, DM>(bp, grid, lds, stream);
+    return nearfield ? launch_batch_one<N, false, false, true, DM>(bp, grid, lds, stream)
+                     : launch_batch_one<N, false, false, false, DM>(bp, grid, lds, stream);
+}
+
+template <int N>
+hipError_t launch_batch_order(const BatchParams &bp, bool cf, bool env, bool nearfield, int table, unsigned grid,
+                              size_t lds, hipStream_t stream)
+{
+    if (table == kDelayTable) return launch_batch_dm<N, kDelayTable>(bp, cf, env, nearfield, grid, lds, stream);
+    if (table == kDelayTableLanes) return launch_batch_dm<N, kDelayTableLanes>(bp, cf, env, nearfield, grid, lds, stream);
+    return launch_batch_dm<N, kDelayComputed>(bp, cf, env, nearfield, grid, lds, stream);
 }
 
 template <int N>
 hipError_t launch_order(const KernelParams *p, const LaunchShape &s, hipStream_t stream, int *blocks)
 {
-#define DMAS_CASE(CF, ENV, NEAR, LIN, ACC)                                                   \
-    if (s.cf == CF && s.env == ENV && s.nearfield == NEAR && s.linear == LIN &&           \
+#define DMAS_CASE(CF, ENV, NEAR, DM, ACC)                                                    \
+    if (s.cf == CF && s.env == ENV && s.nearfield == NEAR && s.delay == DM &&             \
         s.accumulate == ACC)                                                              \
-        return p ? launch_one<N, CF, ENV, NEAR, LIN, ACC>(*p, s, stream)                  \
-                 : occupancy_one<N, CF, ENV, NEAR, LIN, ACC>(s, blocks);
-    DMAS_CASE(false, false, false, false, kAccF32)
-    DMAS_CASE(false, true, false, false, kAccF32)
-    DMAS_CASE(true, false, false, false, kAccF32)
-    DMAS_CASE(true, true, false, false, kAccF32)
-    DMAS_CASE(false, false, true, false, kAccF32)
-    DMAS_CASE(false, true, true, false, kAccF32)
-    DMAS_CASE(true, false, true, false, kAccF32)
-    DMAS_CASE(true, true, true, false, kAccF32)
-    DMAS_CASE(true, false, false, true, kAccF32)
-    DMAS_CASE(true, true, false, true, kAccF32)
-    DMAS_CASE(true, false, true, true, kAccF32)
-    DMAS_CASE(true, true, true, true, kAccF32)
-    DMAS_CASE(true, false, false, false, kAccKahan)
-    DMAS_CASE(true, true, false, false, kAccKahan)
-    DMAS_CASE(true, false, false, false, kAccF64)
-    DMAS_CASE(true, true, false, false, kAccF64)
+        return p ? launch_one<N, CF, ENV, NEAR, DM, ACC>(*p, s, stream)                   \
+                 : occupancy_one<N, CF, ENV, NEAR, DM, ACC>(s, blocks);
+#define DMAS_WHOLE(DM)                                          \
+    DMAS_CASE(false, false, false, DM, kAccF32)                 \
+    DMAS_CASE(false, true, false, DM, kAccF32)                  \
+    DMAS_CASE(true, false, false, DM, kAccF32)                  \
+    DMAS_CASE(true, true, false, DM, kAccF32)                   \
+    DMAS_CASE(false, false, true, DM, kAccF32)                  \
+    DMAS_CASE(false, true, true, DM, kAccF32)                   \
+    DMAS_CASE(true, false, true, DM, kAccF32)                   \
+    DMAS_CASE(true, true, true, DM, kAccF32)                    \
+    DMAS_CASE(true, false, false, DM, kAccKahan)                \
+    DMAS_CASE(true, true, false, DM, kAccKahan)                 \
+    DMAS_CASE(true, false, false, DM, kAccF64)                  \
+    DMAS_CASE(true, true, false, DM, kAccF64)
+    DMAS_WHOLE(kDelayTable)
+    DMAS_WHOLE(kDelayTableLanes)
+    DMAS_WHOLE(kDelayComputed)
+    DMAS_CASE(true, false, false, kDelayLinear, kAccF32)
+    DMAS_CASE(true, true, false, kDelayLinear, kAccF32)
+    DMAS_CASE(true, false, true, kDelayLinear, kAccF32)
+    DMAS_CASE(true, true, true, kDelayLinear, kAccF32)
+#undef DMAS_WHOLE
 #undef DMAS_CASE
     return hipErrorNotSupported;
 }

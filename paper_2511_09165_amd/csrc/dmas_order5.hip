@@ -10,9 +10,9 @@ hipError_t launch_order5(const KernelParams *p, const LaunchShape &s, hipStream_
     return launch_order<5>(p, s, stream, blocks);
 }
 
-hipError_t launch_batch_order5(const BatchParams &bp, bool cf, bool env, bool nearfield, unsigned grid,
-                               size_t lds, hipStream_t stream)
+hipError_t launch_batch_order5(const BatchParams &bp, bool cf, bool env, bool nearfield, int table,
+                               unsigned grid, size_t lds, hipStream_t stream)
 {
-    return launch_batch_order<5>(bp, cf, env, nearfield, grid, lds, stream);
+    return launch_batch_order<5>(bp, cf, env, nearfield, table, grid, lds, stream);
 }
 }  // namespace dmas

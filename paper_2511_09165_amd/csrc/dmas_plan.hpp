@@ -31,7 +31,7 @@ struct dmas_plan_s {
     double *d_mic = nullptr;
     double *d_dirs = nullptr;
     int32_t *d_tiles = nullptr;
-    uint16_t *d_tile_rel = nullptr;   // per-tile delay tables (M > 64, whole-sample delays), or null
+    int32_t *d_tile_off = nullptr;    // per-tile delay tables (whole-sample delays), or null
     int32_t *d_tile_dref = nullptr;
     float *d_taps = nullptr;
     int env_decim = 1;
@@ -65,7 +65,7 @@ inline KernelParams make_params(const dmas_plan_s *plan, const void *d_x, const 
     kp.mic = plan->d_mic;
     kp.dirs = plan->d_dirs;
     kp.tile_dirs = plan->d_tiles;
-    kp.tile_rel = plan->d_tile_rel;
+    kp.tile_off = plan->d_tile_off;
     kp.tile_dref = plan->d_tile_dref;
     kp.taps = plan->d_taps;
     kp.M = plan->M;
@@ -96,7 +96,10 @@ inline LaunchShape shape_of(const dmas_plan_s *p, bool env)
     ls.cf = p->cf;
     ls.env = env;
     ls.nearfield = p->nearfield;
-    ls.linear = p->linear;
+    ls.delay = p->linear ? kDelayLinear
+               : !p->d_tile_off ? kDelayComputed
+               : p->M <= kWaveSize ? kDelayTable
+                                   : kDelayTableLanes;
     ls.accumulate = p->compensated;
     ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
     ls.lds_bytes = env ? p->lds_env : p->lds_rf;

@@ -146,7 +146,8 @@ bool batchable(const dmas_plan_s *p)
 bool same_class(const Frame *a, const Frame *b)
 {
     return a->env == b->env && a->plan->order == b->plan->order && a->plan->cf == b->plan->cf &&
-           a->plan->nearfield == b->plan->nearfield;
+           a->plan->nearfield == b->plan->nearfield &&
+           dmas::shape_of(a->plan, a->env).delay == dmas::shape_of(b->plan, b->env).delay;
 }
 
 dmas_status_t srv_fail(dmas_status_t st, const char *msg)
@@ -400,7 +401,8 @@ struct dmas_server_s {
                             bp.starts = reinterpret_cast<const int32_t *>(d_tables[s] + sizeof(dmas::KernelParams) * nf);
                             bp.num_frames = nf;
                             e = dmas::launch_batch(head->plan->order, bp, head->plan->cf, head->env,
-                                                   head->plan->nearfield, (unsigned)total, lds, st);
+                                                   head->plan->nearfield, dmas::shape_of(head->plan, head->env).delay,
+                                                   (unsigned)total, lds, st);
                         }
                     }
                 }

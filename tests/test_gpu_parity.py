@@ -141,13 +141,15 @@ def test_microphone_blocks(nearfield):
     _compare(f, f.x_f32())
 
 
+@pytest.mark.parametrize("M", [24, 150])
 @pytest.mark.parametrize("nearfield", [False, True])
 @pytest.mark.parametrize("n", [1, 3, 5])
-def test_delay_table_matches_per_block_delays(n, nearfield, monkeypatch):
-    """With M > 64 the plan keeps per-tile delay tables; the images equal, bit for bit, those of a
-    plan that evaluates eq. (1) per microphone block instead (DMAS_NO_DELAY_TABLE)."""
-    f = synth.random_frame(np.random.default_rng(8 + n), 150, 37, 900, n, nearfield=nearfield)
-    _say(f"delay table n={n} near={nearfield}")
+def test_delay_table_matches_per_block_delays(n, nearfield, M, monkeypatch):
+    """Plans with whole-sample delays keep per-tile delay tables; the images equal, bit for bit,
+    those of a plan that evaluates eq. (1) on the device instead (DMAS_NO_DELAY_TABLE): once per
+    workgroup for M <= 64, per microphone block beyond."""
+    f = synth.random_frame(np.random.default_rng(8 + n + M), M, 37, 900, n, nearfield=nearfield)
+    _say(f"delay table n={n} near={nearfield} M={M}")
     a = _run(f, f.x_f32(), env=True)
     monkeypatch.setenv("DMAS_NO_DELAY_TABLE", "1")
     b = _run(f, f.x_f32(), env=True)
