@@ -135,6 +135,8 @@ typedef struct {
     int32_t lds_bytes;         /* dynamic LDS per workgroup */
     int32_t fir_len;
     int64_t workgroups;        /* per launch */
+    int64_t delay_table_bytes; /* device memory of the plan's per-tile delay tables
+                                  (0: delays are evaluated on the device) */
 } dmas_plan_info_t;
 
 /* Fill *desc with defaults: far field, FP32 input, CF on, nearest delays,
@@ -142,11 +144,14 @@ typedef struct {
 dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *desc);
 
 /* Validate *desc, copy geometry and taps to the current device, choose the
- * tiling. On success *out receives the plan. n > M, an even fir_len and a
+ * tiling, and for whole-sample delays build per-tile delay tables on the
+ * device (36 bytes per tile of 8 directions and microphone; skipped above
+ * 2 GiB). Synchronises the null stream. On success *out receives the plan. n > M, an even fir_len and a
  * non-unit far-field direction (| |u| - 1 | > 1e-6) are DMAS_ERR_INVALID_ARG. */
 dmas_status_t dmas_plan_create(const dmas_plan_desc_t *desc, dmas_plan_t *out);
 
-/* Release a plan. NULL is a no-op. */
+/* Release a plan and its device memory. NULL is a no-op. Work queued with
+ * the plan must have completed (the caller synchronises its streams first). */
 dmas_status_t dmas_plan_destroy(dmas_plan_t plan);
 
 dmas_status_t dmas_plan_query(dmas_plan_t plan, dmas_plan_info_t *info);

@@ -732,6 +732,7 @@ dmas_status_t dmas_plan_query(dmas_plan_t p, dmas_plan_info_t *info)
     info->lds_bytes = (int32_t)p->lds_env;
     info->fir_len = p->fir_len;
     info->workgroups = (int64_t)p->num_tiles * p->nseg_env;
+    info->delay_table_bytes = p->d_tile_off ? (int64_t)p->num_tiles * p->M * (dmas::kDirsPerTile + 1) * 4 : 0;
     return DMAS_OK;
 }
 

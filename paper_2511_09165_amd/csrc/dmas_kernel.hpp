@@ -10,25 +10,32 @@
 //
 // Work decomposition (MI355X-first; not the paper's one-thread-per-pixel CUDA
 // design):
+//   * With whole-sample delays the root of a delayed sample is the root of a
+//     channel sample, so a separate pass (root_plane_kernel) writes each
+//     channel sample's (root, sample) pair once; the beamformer stages those.
 //   * A workgroup owns one tile of kDirsPerTile nearby directions (one wave per
 //     direction) and one time segment. Directions were grouped on the host so
 //     that their steering delays stay within +-halo samples of the tile's first
 //     (reference) direction.
 //   * The segment is walked in chunks of kChunk samples. For each chunk the
-//     workgroup stages, per microphone, one window of the channel
+//     workgroup stages, per microphone, one window
 //     [t0 + d_ref - halo, t0 + d_ref - halo + row) into LDS (zero outside the
 //     record); every wave then reads its own delayed samples from that window
 //     with a wave-uniform offset, so one staged window serves all directions
 //     of the tile. Microphones are staged in blocks of <= 64 when M is large.
+//   * Window offsets come from per-tile tables built at plan creation (read
+//     through the scalar cache when small) or are computed from the geometry.
 //   * Each lane owns kSamplesPerLane output samples at stride 64 and keeps
 //     their power sums in registers across all microphones; the LDS reads of a
 //     wave are contiguous (conflict-free) and the per-microphone address update
 //     is one scalar offset shared by all samples of the lane.
 //   * The epilogue evaluates Newton-Girard, CF and either stores y, or writes
-//     |y| into a per-wave LDS ring and applies the FIR there; the ring keeps
-//     the last L-1 values between chunks so the envelope never round-trips
-//     through HBM and needs only L-1 samples of halo per segment.
-//   * There is no contraction here, so no MFMA: the bound is VALU issue.
+//     |y| into a per-wave LDS ring; the ring keeps the last L-1 values between
+//     chunks so the envelope never round-trips through HBM and needs only L-1
+//     samples of halo per segment.
+//   * The microphone loop is a gather and sum, not a contraction, and runs on
+//     the VALU (its bound); the envelope FIR of a chunk is a Toeplitz matrix
+//     product and runs on the matrix cores in FP32.
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -132,10 +139,10 @@ __device__ __forceinline__ float to_f32(typename StorageOf<DT>::type v)
 }
 
 // One microphone's window [base, base + row) of the channel starting at
-// element chan, converted to FP32, zero outside [0, T). Windows inside the
+// element chan, converted to FP32, zero outside [0, T); used where samples
+// rather than roots are staged (n = 1, linear delays). Windows inside the
 // record (all but the first and last chunks) take a path without per-element
-// bounds checks. (Issuing several loads before their LDS stores measured 2.5 %
-// slower on the eRTIS-like frame; one load per step is kept.)
+// bounds checks.
 template <int DT>
 __device__ __forceinline__ void stage_row(float *__restrict__ dst, const void *__restrict__ x, size_t chan,
                                           int base, int row, int T, int lane)

@@ -150,8 +150,13 @@ def test_delay_table_matches_per_block_delays(n, nearfield, M, monkeypatch):
     workgroup for M <= 64, per microphone block beyond."""
     f = synth.random_frame(np.random.default_rng(8 + n + M), M, 37, 900, n, nearfield=nearfield)
     _say(f"delay table n={n} near={nearfield} M={M}")
+    with _plan(f) as plan:
+        info = plan.info()
+    assert info["delay_table_bytes"] == info["num_tiles"] * M * 9 * 4
     a = _run(f, f.x_f32(), env=True)
     monkeypatch.setenv("DMAS_NO_DELAY_TABLE", "1")
+    with _plan(f) as plan:
+        assert plan.info()["delay_table_bytes"] == 0
     b = _run(f, f.x_f32(), env=True)
     assert np.array_equal(a, b)
 
