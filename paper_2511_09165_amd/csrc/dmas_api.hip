@@ -635,13 +635,40 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     const size_t elem = p->roots ? 2 * sizeof(float) : sizeof(float);
     auto lds_for = [&](int m) { return fixed + ring_bytes + elem * (size_t)m * p->row; };
     const int mb_max = std::min(M, dmas::kMaxMicBlock);
-    int mb = 0;
-    for (int per_cu = 3; per_cu >= 1 && mb == 0; --per_cu)
-        for (int cand : {mb_max, 48, 32, 24, 16, 12, 8, 4, 2, 1})
-            if (cand <= mb_max && lds_for(cand) * per_cu <= lds_cap) {
-                mb = cand;
-                break;
-            }
+    // Per-tile delay tables for whole-sample delays, when of modest size (the
+    // delay mode selects the kernel, so it is fixed before the occupancy
+    // queries below).
+    const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
+    p->tables = !p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE");
+    // Microphones per LDS block, from the envelope kernel's occupancy (its
+    // registers, LDS and the wave limit decide): with M <= 64 the largest
+    // block that keeps three workgroups per CU (or as many as any block
+    // reaches), since a whole array takes only a few blocks per chunk; with
+    // more microphones the largest block that reaches the highest occupancy
+    // (measured: 1024 microphones at order 3 run 7 % faster with 12-microphone
+    // blocks at four workgroups per CU than with 16 at three, while 32
+    // microphones run 5 % slower that way).
+    const int occ_target = M <= dmas::kWaveSize ? 3 : 1 << 30;
+    int mb = 0, best_occ = 0;
+    for (int cand : {mb_max, 48, 32, 24, 16, 12, 8, 4, 2, 1}) {
+        if (cand > mb_max || lds_for(cand) > lds_cap) continue;
+        dmas::LaunchShape ls = dmas::shape_of(p, true);
+        ls.lds_bytes = lds_for(cand);
+        int occ = 0;
+        e = dmas::launch_plan(n, nullptr, ls, nullptr, &occ);
+        if (e == hipErrorNotSupported) {   // no kernel for these flags: reported at launch
+            occ = (int)(lds_cap / lds_for(cand));
+            e = hipSuccess;
+        }
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_fail(e, "occupancy query");
+        }
+        if (std::min(occ, occ_target) > best_occ) {
+            best_occ = std::min(occ, occ_target);
+            mb = cand;
+        }
+    }
     if (const char *fixed_mb = std::getenv("DMAS_MIC_BLOCK")) mb = std::max(1, std::min(mb_max, std::atoi(fixed_mb)));
     if (mb == 0 || lds_for(mb) > lds_cap) {
         plan_free(p);
@@ -652,12 +679,10 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->lds_rf = fixed + elem * (size_t)mb * p->row;
     p->lds_env = p->lds_rf + ring_bytes;
 
-    // Per-tile delay tables for whole-sample delays, when of modest size: the
-    // kernel reads window offsets and reference delays through the scalar
-    // cache instead of evaluating eq. (1) on the device and moving the
+    // Build the delay tables: the kernel reads window offsets and reference
+    // delays instead of evaluating eq. (1) on the device and moving the
     // results between lanes.
-    const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
-    if (!p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE")) {
+    if (p->tables) {
         const size_t n_off = (size_t)p->num_tiles * W * M, n_dref = (size_t)p->num_tiles * M;
         e = hipMalloc((void **)&p->d_tile_off, sizeof(int32_t) * n_off);
         if (e == hipSuccess) e = hipMalloc((void **)&p->d_tile_dref, sizeof(int32_t) * n_dref);

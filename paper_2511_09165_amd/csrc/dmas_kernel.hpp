@@ -713,8 +713,17 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 // XCDs, so every XCD's L2 reads the whole root plane once per launch (8 x
 // 4 MiB for the eRTIS-like frame); giving each XCD a contiguous range of
 // segments instead cut those reads to 10 MB but measured 4-5 % slower.
+// Orders up to 3 with FP32 sums fit in 64 VGPRs and the SGPR budget of eight
+// waves per SIMD. With more than 64 microphones (lane-loaded delay tables)
+// asking for that occupancy lets four workgroups share a CU (measured 8 %
+// faster on the 1024-microphone near-field frame); with fewer, LDS keeps the
+// kernel at three workgroups anyway and the tighter register budget only
+// costs (2 % on a 32-microphone frame). Higher orders would spill.
+template <int N, int ACC, int DM>
+constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableLanes) ? 8 : 1;
+
 template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
-__global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, ACC, DM>))
 dmas_kernel(const KernelParams p)
 {
     extern __shared__ float smem[];
@@ -725,7 +734,7 @@ dmas_kernel(const KernelParams p)
 // parameters (all of order N) and the first workgroup index of each frame
 // (ascending); each workgroup finds its frame by binary search.
 template <int N, bool CF, bool ENV, bool NEAR, int DM>
-__global__ void __launch_bounds__(kDirsPerTile * kWaveSize)
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, kAccF32, DM>))
 dmas_batch_kernel(const BatchParams bp)
 {
     extern __shared__ float smem[];

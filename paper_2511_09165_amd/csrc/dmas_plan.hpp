@@ -14,6 +14,7 @@ struct dmas_plan_s {
     int M = 0, T = 0, D = 0, order = 0;
     bool cf = true, nearfield = false, linear = false;
     bool roots = false;    // kernel reads a root plane (whole-sample delays, n >= 2)
+    bool tables = false;   // per-tile delay tables (whole-sample delays, <= 2 GiB)
     int compensated = 0;   // 0 FP32 sums, 1 Kahan FP32, 2 FP64
     int ng_fp64 = 0;
     int dtype = DMAS_F32;
@@ -97,7 +98,7 @@ inline LaunchShape shape_of(const dmas_plan_s *p, bool env)
     ls.env = env;
     ls.nearfield = p->nearfield;
     ls.delay = p->linear ? kDelayLinear
-               : !p->d_tile_off ? kDelayComputed
+               : !p->tables ? kDelayComputed
                : p->M <= kWaveSize ? kDelayTable
                                    : kDelayTableLanes;
     ls.accumulate = p->compensated;
