@@ -179,22 +179,42 @@ void plan_free(dmas_plan_s *p)
     delete p;
 }
 
+// Chunks of samples that the longest of the segments of length s walks. The
+// kernels compute the samples [max(g0 - lead, 0), min(g1 + H, T)) of segment
+// [g0, g1), lead = H rounded up to a multiple of 32 (H = 0 without the
+// envelope). Segments that start at or after `lead` and end at least H before
+// T all walk the same count, so the first few and the last two decide.
+int segment_chunks(int T, int H, int s)
+{
+    const int C = dmas::kChunk, lead = dmas::env_lead(H);
+    const int n = (T + s - 1) / s;
+    int worst = 0;
+    auto walk = [&](int k) {
+        const int g0 = k * s, g1 = std::min(g0 + s, T);
+        worst = std::max(worst, (std::min(g1 + H, T) - std::max(g0 - lead, 0) + C - 1) / C);
+    };
+    for (int k = 0; k < std::min(n, lead / 32 + 2); ++k) walk(k);
+    for (int k = std::max(0, n - 2); k < n; ++k) walk(k);
+    return worst;
+}
+
 // Output samples per workgroup. Every segment is a multiple of 32 samples
-// (aligned output lines) and, with the envelope halo, a whole number of
-// chunks. The count is chosen to minimise (workgroup rounds on the device) x
+// (aligned output lines); a segment away from the record's ends walks
+// s + H + lead samples, and s is the longest that keeps that walk's chunk
+// count. The count is chosen to minimise (workgroup rounds on the device) x
 // (chunks per workgroup): long segments waste little halo, but the last round
 // of workgroups should not leave most CUs idle.
-void choose_segments(int T, int num_tiles, int extra, int64_t slots, int fixed, int *seg, int *nseg)
+void choose_segments(int T, int num_tiles, int H, int64_t slots, int fixed, int *seg, int *nseg)
 {
     const int C = dmas::kChunk;
+    const int extra = H + dmas::env_lead(H);
     auto shape = [&](int want, int *s_out, int *n_out, int *chunks_out) {
-        int s = (T + want - 1) / want;
-        s = (s + 31) & ~31;
+        int s = ((T + want - 1) / want + 31) & ~31;
         const int chunks = (s + extra + C - 1) / C;
         s = std::max(32, (chunks * C - extra) & ~31);
         *s_out = s;
         *n_out = (T + s - 1) / s;
-        *chunks_out = (s + extra + C - 1) / C;
+        *chunks_out = segment_chunks(T, H, s);
     };
     if (fixed > 0) {
         *seg = (fixed + 31) & ~31;
@@ -702,7 +722,6 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
 
     const char *fixed_seg = std::getenv("DMAS_SEGMENT");
     const int seg_override = fixed_seg ? std::atoi(fixed_seg) : 0;
-    const int extra_env = 2 * H + (32 - (2 * H) % 32) % 32;
     p->nseg_rf = p->nseg_env = 1;   // dmas::shape_of() needs a grid; the occupancy query ignores it
     for (int env = 0; env < 2; ++env) {
         int blocks = 0;
@@ -713,7 +732,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         }
         const int64_t slots = (int64_t)prop.multiProcessorCount * std::max(1, blocks);
         if (env)
-            choose_segments(T, p->num_tiles, extra_env, slots, seg_override, &p->seg_env, &p->nseg_env);
+            choose_segments(T, p->num_tiles, H, slots, seg_override, &p->seg_env, &p->nseg_env);
         else
             choose_segments(T, p->num_tiles, 0, slots, seg_override, &p->seg_rf, &p->nseg_rf);
         if (env) p->occ_env = blocks; else p->occ_rf = blocks;

@@ -74,16 +74,28 @@ constexpr int kDirsPerTile = 8;
 constexpr int kSamplesPerLane = 4;
 constexpr int kChunk = kWaveSize * kSamplesPerLane;
 
+// Envelope chunk walk: the chunk of samples [tc, tc + kChunk) (tc a multiple
+// of 32) yields the envelope outputs [tc - env_lead(H), ... + kChunk), where
+// env_lead(H) is H rounded up to a multiple of 32, so every output block
+// starts on a 128-byte line. The ring then keeps the env_prefix(H) values of
+// |y| before the chunk.
+__host__ __device__ constexpr int env_lead(int H) { return (H + 31) & ~31; }
+__host__ __device__ constexpr int env_prefix(int H) { return H + env_lead(H); }
+
 // Envelope LDS of a workgroup (floats), after the windows and reference
 // delays: a taps table of env_taps_len(H) floats (kTapLead zeros, the L =
 // 2H + 1 taps, zeros), then one ring per wave of ring_stride(H) floats. The
-// ring holds |y| for ring index i in [0, kChunk + 2H) at float i + i / 16;
-// the skew keeps the FIR's matrix-operand reads (16 indices 16 apart) on
-// distinct LDS banks. The FIR is a product with K = 2H + 16 in steps of 4.
+// ring holds |y| for ring index i in [0, env_prefix(H) + kChunk) at float
+// i + i / 16; the skew keeps the FIR's matrix-operand reads (16 indices 16
+// apart) on distinct LDS banks. The FIR is a product with K = 2H + 16 in steps
+// of 4 and reads ring indices up to 2H + kChunk + 2 (zero beyond the chunk).
 constexpr int kTapLead = 20;
 __host__ __device__ constexpr int env_ksteps(int H) { return (2 * H + 16 + 3) / 4; }
 __host__ __device__ constexpr int env_taps_len(int H) { return (kTapLead + 2 * H + 1 + 16 + 3) & ~3; }
-__host__ __device__ constexpr int ring_logical(int H) { return kChunk + 2 * H + 8; }
+__host__ __device__ constexpr int ring_logical(int H)
+{
+    return kChunk + (env_prefix(H) > 2 * H + 8 ? env_prefix(H) : 2 * H + 8);
+}
 __host__ __device__ constexpr int ring_stride(int H) { return (ring_logical(H) + ring_logical(H) / 16 + 1 + 3) & ~3; }
 __host__ __device__ constexpr int env_lds_floats(int H, int waves) { return env_taps_len(H) + waves * ring_stride(H); }
 // Envelope taps on the device: fir_len taps, zero-padded to a multiple of 4.

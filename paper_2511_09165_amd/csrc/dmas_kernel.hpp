@@ -445,15 +445,19 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const bool active = dir >= 0;
     const double *vdir = p.dirs + 3 * (active ? dir : dir0);
 
-    // Output blocks of a chunk start at tc - H (envelope) or tc (RF). seg_len is
-    // a multiple of 32 and the envelope start is pulled back by align_shift so
-    // that every block of 64 outputs begins on a 128-byte line.
+    // The workgroup's outputs are [g0, g1) (g0 a multiple of 32). Pass ch
+    // covers the samples [tc, tc + C), tc = ystart + ch * C, and outputs
+    // [tc - lead, tc - lead + C), lead = 0 (RF) or H rounded up to a multiple
+    // of 32 (envelope). |y| vanishes outside [0, T), so a walk that starts at
+    // sample 0 begins on the zeroed ring, samples are computed only up to
+    // min(g1 + H, T), and the outputs still missing after that come from
+    // envelope-only passes (their own samples are unused: zeros).
     const int g0 = seg * p.seg_len;
     const int g1 = min(g0 + p.seg_len, p.T);
-    const int align_shift = ENV ? ((32 - (2 * H) % 32) % 32) : 0;
-    const int ystart = g0 - H - align_shift;
-    const int ylen = (g1 - g0) + 2 * H + align_shift;
-    const int nchunks = (ylen + C - 1) / C;
+    const int lead = ENV ? env_lead(H) : 0;
+    const int ystart = max(g0 - lead, 0);
+    const int nchunks = (min(g1 + H, p.T) - ystart + C - 1) / C;
+    const int npasses = (g1 - ystart + lead + C - 1) / C;   // >= nchunks
     const int nblocks = (p.M + p.mic_block - 1) / p.mic_block;
     const int two_halo = 2 * p.halo;
 
@@ -546,13 +550,88 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         // the first block's barrier makes the taps table visible before any epilogue
     }
 
-    for (int ch = 0; ch < nchunks; ++ch) {
-        const int tc = ystart + ch * C;
-        Acc<N, CF, ACC> acc[K];
+    // Envelope of the outputs [tc - lead, tc - lead + C) from the ring, whose
+    // indices [env_prefix(H), env_prefix(H) + C) hold |y| of the samples
+    // [tc, tc + C); then keep the ring's last env_prefix(H) values.
+    auto envelope_pass = [&](int tc, size_t orow) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // env[t] for t = tc - lead + o, o in [0, C): sum_k h[k] |y[t + H - k]|
+        //   = sum_k h[k] r[2H + o - k], r = the ring (r[i] = |y[tc - H - lead + i]|).
+        // With o = 16j + i (i, j < 16) this is the 16 x 16 matrix product
+        //   F[i][j] = sum_m G[i][m] R[m][j],  G[i][m] = h[i + 2H - m] (zero
+        //   outside the taps),  R[m][j] = r[16j + m],  m < 2H + 16,
+        // done on the matrix cores in FP32, K = 4 per step: lane l holds
+        // G[l % 16][4kk + l / 16] and R[4kk + l / 16][l % 16] and receives
+        // F[4 (l / 16) + v][l % 16], v < 4, i.e. the four consecutive
+        // outputs o = 16 (l % 16) + 4 (l / 16) + v: one 16-byte store per
+        // lane, 1 KiB contiguous per wave.
+        if (p.env_decim == 1) {
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const int g = lane >> 4, c = lane & 15;
+            const float *rb = ring + 17 * c + g;                  // r[16c + g], skewed
+            const float *ha = tap_lds + kTapLead + c + 2 * H - g; // h[c + 2H - g]
+            const int ks = env_ksteps(H);
+            v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
+            int kk = 0;
+            for (; kk + 1 < ks; kk += 2) {
+                e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+                e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)],
+                                                          e1, 0, 0, 0);
+            }
+            if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+            const v4f e = e0 + e1;
+            const int t0 = tc - lead + 16 * c + 4 * g;   // a multiple of 4 (tc - lead is one of 32)
+            float *dst = p.out + orow + t0;
+            if (t0 >= g0 && t0 + 3 < g1 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+                __builtin_nontemporal_store(e, reinterpret_cast<v4f *>(dst));
+            } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j) acc[j].zero();
+                for (int v = 0; v < 4; ++v)
+                    if (t0 + v >= g0 && t0 + v < g1) __builtin_nontemporal_store(e[v], dst + v);
+            }
+        } else {
+            // Decimated envelope: only the outputs at t = j * env_decim, each
+            // owned by the segment that contains t.
+            const int dec = p.env_decim;
+            const int t_lo = tc - lead;
+            const int lo = max(t_lo, g0);
+            const int hi = min(t_lo + C, g1);
+            if (hi > lo) {
+                const int j0 = (lo + dec - 1) / dec;   // lo >= 0
+                const int j1 = (hi + dec - 1) / dec;
+                for (int jo = j0 + lane; jo < j1; jo += kWaveSize) {
+                    const int i0 = 2 * H + (jo * dec - t_lo);
+                    float e = 0.0f;
+                    for (int k = 0; k < p.fir_len; ++k) {
+                        const int ri = i0 - k;
+                        e = __builtin_fmaf(taps[k], ring[ri + (ri >> 4)], e);
+                    }
+                    __builtin_nontemporal_store(e, p.out + orow + jo);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // keep the last env_prefix(H) values of |y| for the next pass (<= C: no overlap)
+        for (int i = lane; i < env_prefix(H); i += kWaveSize) ring[i + (i >> 4)] = ring[C + i + ((C + i) >> 4)];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
 
-        for (int blk = 0; blk < nblocks; ++blk) {
+    // Power sums: cleared here and right after each epilogue reads them
+    // (clearing them at the top of every pass made the compiler emit the
+    // clears on both sides of the `compute` branch: measured 1.6 % slower).
+    Acc<N, CF, ACC> acc[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j].zero();
+    for (int ch = 0; ch < npasses; ++ch) {
+        const int tc = ystart + ch * C;
+        // Passes after the last computed chunk are envelope-only: their samples
+        // lie past T (zero) or feed only outputs past g1, and enter the ring as zeros.
+        const bool compute = ch < nchunks;
+
+        for (int blk = 0; blk < (compute ? nblocks : 0); ++blk) {
             if (!all_mics) block_geometry(blk);
             __syncthreads();  // reference delays visible; previous block's reads done
             block_offsets(blk);
@@ -630,6 +709,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
                 const float y = finish_pixel<N, CF, ACC>(acc[j], p);
+                acc[j].zero();
                 if (t < g1) __builtin_nontemporal_store(y, p.out + orow + t);
             }
         } else {
@@ -637,72 +717,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
                 const float y = finish_pixel<N, CF, ACC>(acc[j], p);
-                const int ri = 2 * H + lane + kWaveSize * j;
-                ring[ri + (ri >> 4)] = (t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
+                acc[j].zero();
+                const int ri = env_prefix(H) + lane + kWaveSize * j;
+                ring[ri + (ri >> 4)] = (compute && t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            // env[t] for t = tc - H + o, o in [0, C): sum_k h[k] |y[t + H - k]|
-            //   = sum_k h[k] r[2H + o - k], r = the ring.
-            // With o = 16j + i (i, j < 16) this is the 16 x 16 matrix product
-            //   F[i][j] = sum_m G[i][m] R[m][j],  G[i][m] = h[i + 2H - m] (zero
-            //   outside the taps),  R[m][j] = r[16j + m],  m < 2H + 16,
-            // done on the matrix cores in FP32, K = 4 per step: lane l holds
-            // G[l % 16][4kk + l / 16] and R[4kk + l / 16][l % 16] and receives
-            // F[4 (l / 16) + v][l % 16], v < 4, i.e. the four consecutive
-            // outputs o = 16 (l % 16) + 4 (l / 16) + v: one 16-byte store per
-            // lane, 1 KiB contiguous per wave.
-            if (p.env_decim == 1) {
-                typedef float v4f __attribute__((ext_vector_type(4)));
-                const int g = lane >> 4, c = lane & 15;
-                const float *rb = ring + 17 * c + g;                  // r[16c + g], skewed
-                const float *ha = tap_lds + kTapLead + c + 2 * H - g; // h[c + 2H - g]
-                const int ks = env_ksteps(H);
-                v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
-                int kk = 0;
-                for (; kk + 1 < ks; kk += 2) {
-                    e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
-                    e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)],
-                                                              e1, 0, 0, 0);
-                }
-                if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
-                const v4f e = e0 + e1;
-                const int t0 = tc - H + 16 * c + 4 * g;   // a multiple of 4 (tc - H is one of 32)
-                float *dst = p.out + orow + t0;
-                if (t0 >= g0 && t0 + 3 < g1 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-                    __builtin_nontemporal_store(e, reinterpret_cast<v4f *>(dst));
-                } else {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (t0 + v >= g0 && t0 + v < g1) __builtin_nontemporal_store(e[v], dst + v);
-                }
-            } else {
-                // Decimated envelope: only the outputs at t = j * env_decim, each
-                // owned by the segment that contains t.
-                const int dec = p.env_decim;
-                const int t_lo = tc - H;
-                const int lo = max(t_lo, g0);
-                const int hi = min(t_lo + C, g1);
-                if (hi > lo) {
-                    const int j0 = (lo + dec - 1) / dec;   // lo >= 0
-                    const int j1 = (hi + dec - 1) / dec;
-                    for (int jo = j0 + lane; jo < j1; jo += kWaveSize) {
-                        const int i0 = 2 * H + (jo * dec - t_lo);
-                        float e = 0.0f;
-                        for (int k = 0; k < p.fir_len; ++k) {
-                            const int ri = i0 - k;
-                            e = __builtin_fmaf(taps[k], ring[ri + (ri >> 4)], e);
-                        }
-                        __builtin_nontemporal_store(e, p.out + orow + jo);
-                    }
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            // keep the last 2H values of |y| for the next chunk (2H <= C: no overlap)
-            for (int i = lane; i < 2 * H; i += kWaveSize) ring[i + (i >> 4)] = ring[C + i + ((C + i) >> 4)];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            envelope_pass(tc, orow);
         }
     }
 }

@@ -390,6 +390,28 @@ def test_envelope_fir_lengths(L, T):
     check_t1(dec, env[:, ::3], tol=1e-5)
 
 
+@pytest.mark.parametrize(
+    "L,T,seg",
+    [(255, 997, 32), (255, 997, 96), (127, 1000, 160), (63, 2048, 2240), (63, 2048, 992), (31, 700, 160),
+     (1, 300, 64), (63, 33, 32)],
+)
+def test_envelope_segment_walks(L, T, seg, monkeypatch):
+    """Envelope over forced segment lengths: segments that start before the FIR lead (walk clipped
+    at sample 0), envelope-only passes after the last computed chunk, one-segment records."""
+    monkeypatch.setenv("DMAS_SEGMENT", str(seg))
+    f = synth.random_frame(np.random.default_rng(500 + L + T), 12, 21, T, 3)
+    taps = np.random.default_rng(600 + L).normal(size=L).astype(np.float32)
+    _say(f"segment walk L={L} T={T} seg={seg}")
+    with _plan(f, fir_taps=taps) as plan:
+        assert plan.info()["segment"] == seg
+    env = _run(f, f.x_f32(), env=True, taps=taps)
+    y_ref = oracle.frame_rows(f, x=f.x_f32().astype(np.float64))
+    env_ref = oracle.envelope(y_ref, taps.astype(np.float64))
+    check_t1(env, env_ref)
+    dec = _run(f, f.x_f32(), env=True, taps=taps, env_decimation=5)
+    check_t1(dec, env[:, ::5], tol=1e-5)
+
+
 def test_plan_rejects_bad_pipeline_options():
     from paper_2511_09165_amd import DmasError
     f = synth.random_frame(np.random.default_rng(96), 8, 5, 100, 2)
