@@ -732,14 +732,25 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 // XCDs, so every XCD's L2 reads the whole root plane once per launch (8 x
 // 4 MiB for the eRTIS-like frame); giving each XCD a contiguous range of
 // segments instead cut those reads to 10 MB but measured 4-5 % slower.
-// Orders up to 3 with FP32 sums fit in 64 VGPRs and the SGPR budget of eight
-// waves per SIMD. With more than 64 microphones (lane-loaded delay tables)
-// asking for that occupancy lets four workgroups share a CU (measured 8 %
-// faster on the 1024-microphone near-field frame); with fewer, LDS keeps the
-// kernel at three workgroups anyway and the tighter register budget only
-// costs (2 % on a 32-microphone frame). Higher orders would spill.
+//
+// Register budget: the kernel is compiled for kMinWavesPerSimd waves per SIMD
+// (512 / waves VGPRs; a workgroup puts two waves on each SIMD).
+//  * 8 (64 VGPRs): orders up to 3 with FP32 sums fit it, SGPRs included. With
+//    more than 64 microphones (lane-loaded delay tables) that lets four
+//    workgroups share a CU (measured 8 % faster on the 1024-microphone
+//    near-field frame); with fewer, LDS keeps the kernel at three workgroups
+//    anyway and the tighter budget only costs (2 % on a 32-microphone frame).
+//  * 6 (80 VGPRs, three workgroups per CU): orders 7 and 8 with FP32 sums
+//    (83 and 95 VGPRs unconstrained) and Kahan / FP64 sums up to order 5 with
+//    scalar-cache tables (87-89). The cap spills 16-56 bytes per lane, which
+//    costs less than the third workgroup gains: 9-17 % faster on the
+//    32-microphone frame, 10 % on the near-field frame at order 7.
+//  * none otherwise: Kahan / FP64 sums at orders 6-8 spill 90-280 bytes under
+//    the cap and ran 1.2-6x slower.
 template <int N, int ACC, int DM>
-constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableLanes) ? 8 : 1;
+constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableLanes)     ? 8
+                                 : ACC == kAccF32 ? (N >= 6 ? 6 : 1)
+                                 : (N <= 5 && DM == kDelayTable) ? 6 : 1;
 
 template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
 __global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, ACC, DM>))
