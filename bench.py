@@ -38,6 +38,8 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 # Issue cost of the gfx950 transcendentals (v_exp_f32 / v_log_f32 / v_sqrt_f32)
 # in full-rate slots, measured (half rate).
 TRANS_SLOTS = 2
+# Dense FP32 matrix-core peak of MI355X (published), for the matched filter.
+MFMA_F32_FLOPS = 157.3e12
 
 
 def mic_slots(n: int, cf: bool) -> int:
@@ -260,6 +262,90 @@ def bench_nearfield(args) -> dict:
     return rec
 
 
+def linear_pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
+    """Slots per pixel with linear fractional delays: per microphone the interpolation (subtract,
+    FMA) and the signed root of the interpolated value (a root of a channel sample cannot be
+    reused), then the same powers and sums, Newton-Girard, CF and envelope as ``pixel_slots``."""
+    return pixel_slots(M, n, cf, fir_len) + M * (2 + root_slots(n))
+
+
+def bench_linear(args) -> dict:
+    """Order-5 DMAS + CF + envelope on the eRTIS-like frame with linear fractional delays."""
+    import torch
+
+    import synth
+    from paper_2511_09165_amd import plan_for_frame
+
+    frame = synth.config2()
+    M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
+    fir_len = 63
+    with plan_for_frame(frame, fir_len=fir_len, linear=True) as plan:
+        x = torch.from_numpy(frame.x_f32()).cuda()
+        out = torch.empty((D, T), dtype=torch.float32, device="cuda")
+        stream = torch.cuda.current_stream()
+        steps = max(5, args.steps // 5)
+        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, max(2, args.warmup // 5), stream)
+        info = plan.info()
+    pixels = D * T
+    rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
+        "workload": "eRTIS-like frame with linear fractional delays: order-5 DMAS+CF+envelope, M=32, "
+                    "91x46 az/el directions, T=16384 at 450 kHz, 63-tap envelope FIR",
+        "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len, "delays": "linear"})
+    rec["metric"] = "direction*samples/sec, order-5 DMAS+CF, 32 mics, linear fractional delays"
+    rec["steps"] = steps
+    rec["roofline"] = _roofline(D * T * linear_pixel_slots(M, n, True, fir_len), pixels, kernel_ms)
+    rec["extra"] = {"plan": info}
+    return rec
+
+
+def bench_pipeline(args) -> dict:
+    """Raw channels -> matched filter (450-tap chirp) -> order-5 DMAS + CF -> envelope kept every
+    20th sample, on the eRTIS-like frame: the steps either side of the beamformer."""
+    import torch
+
+    import synth
+    from paper_2511_09165_amd import plan_for_frame
+
+    frame = synth.config2(matched=False)
+    M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
+    fir_len, decim = 63, 20
+    pulse = frame.truth["pulse"].astype(np.float32)
+    P = pulse.size
+    with plan_for_frame(frame, fir_len=fir_len, mf_pulse=pulse, env_decimation=decim) as plan:
+        raw = torch.from_numpy(frame.x_f32()).cuda()
+        x = torch.empty_like(raw)
+        out = torch.empty((D, -(-T // decim)), dtype=torch.float32, device="cuda")
+        stream = torch.cuda.current_stream()
+
+        def step():
+            plan.matched_filter(raw, out=x)
+            plan.envelope(x, out=out)
+
+        steps = max(5, args.steps // 5)
+        ms_per_step, step_ms = _timed(step, steps, max(2, args.warmup // 5), stream)
+        mf_ms = _timed(lambda: plan.matched_filter(raw, out=x), steps, 2, stream)[1]
+        env_ms = _timed(lambda: plan.envelope(x, out=out), steps, 2, stream)[1]
+        info = plan.info()
+    pixels = D * T
+    env_slots = (D * T * (pixel_slots(M, n, True, fir_len) - fir_len) + D * (-(-T // decim)) * fir_len
+                 + M * T * root_slots(n))
+    rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
+        "workload": "raw eRTIS-like frame -> matched filter (450-sample 25-75 kHz chirp) -> order-5 DMAS+CF -> "
+                    "63-tap envelope kept every 20th sample; M=32, 91x46 directions, T=16384 at 450 kHz",
+        "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len, "env_decimation": decim,
+        "mf_len": P})
+    rec["metric"] = "direction*samples/sec, raw -> matched filter -> order-5 DMAS+CF -> decimated envelope"
+    rec["steps"] = steps
+    rec["roofline"] = _roofline(env_slots, pixels, env_ms)
+    mf_flops = 2.0 * M * T * P
+    rec["matched_filter"] = {"kernel_ms": mf_ms, "bound": "mfma", "achieved": mf_flops / (mf_ms * 1e-3) / 1e12,
+                             "peak": MFMA_F32_FLOPS / 1e12, "unit": "TFLOP/s",
+                             "frac": mf_flops / (mf_ms * 1e-3) / MFMA_F32_FLOPS,
+                             "op": "FP32 multiply-add of the correlation, 2 flops"}
+    rec["extra"] = {"step_kernel_ms": step_ms, "envelope_ms": env_ms, "plan": info}
+    return rec
+
+
 def bench_precision(args) -> list:
     """Throughput of the precision forms at the eRTIS-like frame's shape, orders 2..7."""
     import torch
@@ -386,9 +472,12 @@ def main(argv=None) -> int:
     ap.add_argument("--serving-rates", default="500,1000,2000,3000,4000", help="offered frames/s (serving)")
     ap.add_argument("--serving-duration", type=float, default=2.0, help="seconds of arrivals per rate (serving)")
     ap.add_argument("--serving-pool", type=int, default=48, help="distinct frames in the serving pool")
-    ap.add_argument("--workload", default="erti32", choices=["erti32", "nearfield", "precision", "serving"],
+    ap.add_argument("--workload", default="erti32",
+                    choices=["erti32", "nearfield", "precision", "serving", "linear", "pipeline"],
                     help="erti32: the headline frame (default); nearfield: 1024-mic voxel imaging; "
-                         "precision: FP16/BF16 storage, FP64 Newton-Girard and Kahan sums, orders 2-7")
+                         "precision: FP16/BF16 storage, FP64 Newton-Girard and Kahan sums, orders 2-7; "
+                         "linear: the headline frame with linear fractional delays; pipeline: raw channels "
+                         "-> matched filter -> DMAS+CF -> decimated envelope")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also time FP64 Newton-Girard and print the plan")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -422,6 +511,10 @@ def main(argv=None) -> int:
         print(json.dumps(bench_nearfield(args)), flush=True)
     elif args.workload == "serving":
         bench_serving(args)
+    elif args.workload == "linear":
+        print(json.dumps(bench_linear(args)), flush=True)
+    elif args.workload == "pipeline":
+        print(json.dumps(bench_pipeline(args)), flush=True)
     else:
         for r in bench_precision(args):
             print(json.dumps(r), flush=True)

@@ -182,7 +182,10 @@ dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env,
  * beamformer, Section II): d_x[i*T + t] = sum_{k < mf_len} d_raw[i*T + t + k]
  * * pulse[k], raw = 0 beyond the record. d_raw and d_x are M x T FP32 device
  * arrays (the plan must have in_dtype F32 and a pulse); d_x is then the input
- * of dmas_beamform / dmas_envelope. FP32 accumulation in index order. */
+ * of dmas_beamform / dmas_envelope. FP32 products and sums on the matrix
+ * cores (four taps per step, steps in tap order), so each output is within
+ * the usual dot-product bound of its exact value; a non-finite raw sample
+ * also reaches up to 18 outputs before those that use it. */
 dmas_status_t dmas_matched_filter(dmas_plan_t plan, const float *d_raw, float *d_x, void *stream);
 
 /* The steering delays the beamformer uses, eq. (1), computed by the same

@@ -566,22 +566,22 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         // F[4 (l / 16) + v][l % 16], v < 4, i.e. the four consecutive
         // outputs o = 16 (l % 16) + 4 (l / 16) + v: one 16-byte store per
         // lane, 1 KiB contiguous per wave.
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        const int g = lane >> 4, c = lane & 15;
+        const float *rb = ring + 17 * c + g;                  // r[16c + g], skewed
+        const float *ha = tap_lds + kTapLead + c + 2 * H - g; // h[c + 2H - g]
+        const int ks = env_ksteps(H);
+        v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        int kk = 0;
+        for (; kk + 1 < ks; kk += 2) {
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)],
+                                                      e1, 0, 0, 0);
+        }
+        if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+        const v4f e = e0 + e1;
+        const int t0 = tc - lead + 16 * c + 4 * g;   // a multiple of 4 (tc - lead is one of 32)
         if (p.env_decim == 1) {
-            typedef float v4f __attribute__((ext_vector_type(4)));
-            const int g = lane >> 4, c = lane & 15;
-            const float *rb = ring + 17 * c + g;                  // r[16c + g], skewed
-            const float *ha = tap_lds + kTapLead + c + 2 * H - g; // h[c + 2H - g]
-            const int ks = env_ksteps(H);
-            v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
-            int kk = 0;
-            for (; kk + 1 < ks; kk += 2) {
-                e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
-                e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)],
-                                                          e1, 0, 0, 0);
-            }
-            if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
-            const v4f e = e0 + e1;
-            const int t0 = tc - lead + 16 * c + 4 * g;   // a multiple of 4 (tc - lead is one of 32)
             float *dst = p.out + orow + t0;
             if (t0 >= g0 && t0 + 3 < g1 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
                 __builtin_nontemporal_store(e, reinterpret_cast<v4f *>(dst));
@@ -590,25 +590,16 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                 for (int v = 0; v < 4; ++v)
                     if (t0 + v >= g0 && t0 + v < g1) __builtin_nontemporal_store(e[v], dst + v);
             }
-        } else {
-            // Decimated envelope: only the outputs at t = j * env_decim, each
-            // owned by the segment that contains t.
+        } else if (t0 < g1 && t0 + 3 >= g0) {
+            // Decimated envelope: keep the outputs at t = j * env_decim, each owned
+            // by the segment that contains t (t0 >= g0 >= 0 here: both are
+            // multiples of 4).
             const int dec = p.env_decim;
-            const int t_lo = tc - lead;
-            const int lo = max(t_lo, g0);
-            const int hi = min(t_lo + C, g1);
-            if (hi > lo) {
-                const int j0 = (lo + dec - 1) / dec;   // lo >= 0
-                const int j1 = (hi + dec - 1) / dec;
-                for (int jo = j0 + lane; jo < j1; jo += kWaveSize) {
-                    const int i0 = 2 * H + (jo * dec - t_lo);
-                    float e = 0.0f;
-                    for (int k = 0; k < p.fir_len; ++k) {
-                        const int ri = i0 - k;
-                        e = __builtin_fmaf(taps[k], ring[ri + (ri >> 4)], e);
-                    }
-                    __builtin_nontemporal_store(e, p.out + orow + jo);
-                }
+            const int tend = min(t0 + 4, g1);
+            for (int j = (t0 + dec - 1) / dec; j * dec < tend; ++j) {
+                const int v = j * dec - t0;
+                const float ev = v == 0 ? e[0] : v == 1 ? e[1] : v == 2 ? e[2] : e[3];
+                __builtin_nontemporal_store(ev, p.out + orow + j);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

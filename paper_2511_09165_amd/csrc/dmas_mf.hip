@@ -1,9 +1,21 @@
 // Matched filter (pulse compression), the pipeline step before the
 // beamformer: out[i][t] = sum_{k<P} raw[i][t + k] * pulse[k], raw = 0 beyond
-// the record. One workgroup = 256 consecutive outputs of one channel; the
-// input window (256 + P - 1 samples) and the pulse are staged in LDS in
-// pieces of at most 2048 taps, and every thread accumulates its output in
-// FP32 in tap order.
+// the record.
+//
+// Per channel this is a correlation with a P-tap pulse, i.e. a dense Toeplitz
+// product, so it runs on the matrix cores in FP32. A wave owns 256
+// consecutive outputs t0 + o, o = 16j + i (i, j < 16), and computes
+//   F[i][j] = sum_m G[i][m] R[m][j],  G[i][m] = pulse[m - i] (zero outside
+//   [0, P)),  R[m][j] = raw[t0 + 16j + m],  m < P + 15,
+// with v_mfma_f32_16x16x4f32 in K steps of 4: lane l supplies
+// G[l % 16][4kk + l / 16] and R[4kk + l / 16][l % 16] and receives
+// F[4 (l / 16) + v][l % 16], v < 4, the four consecutive outputs
+// o = 16 (l % 16) + 4 (l / 16) + v (one 16-byte store). A workgroup of four
+// waves covers 1024 outputs of one channel and shares one LDS window of the
+// channel (index i stored at i + i / 16, so the 16 columns of an operand,
+// 16 samples apart, fall on distinct banks) and a zero-padded copy of the
+// pulse; pulses longer than kMfTaps run in pieces that add into the same
+// accumulators.
 #include <hip/hip_runtime.h>
 
 #include "dmas_internal.hpp"
@@ -12,32 +24,67 @@ namespace dmas {
 
 namespace {
 
-constexpr int kMfOut = 256;      // outputs per workgroup (= threads)
-constexpr int kMfTaps = 2048;    // taps staged per pass
+constexpr int kMfWaves = 4;
+constexpr int kMfBlock = 256;                    // outputs per wave
+constexpr int kMfOut = kMfWaves * kMfBlock;      // outputs per workgroup
+constexpr int kMfTaps = 2048;                    // pulse taps per piece
+constexpr int kMfLead = 16;                      // zeros before the pulse (G at m < i)
+// pulse table: kMfLead zeros, the piece's taps, zeros up to the last K step
+constexpr int kMfTapTab = kMfLead + kMfTaps + 20;
+// channel window: every index the last wave's last K step reads
+constexpr int kMfWin = kMfOut + kMfTaps + 20;
+constexpr int kMfWinSkewed = kMfWin + kMfWin / 16 + 1;
 
-__global__ void __launch_bounds__(kMfOut)
+__global__ void __launch_bounds__(kMfWaves * kWaveSize)
 matched_filter_kernel(const float *__restrict__ raw, const float *__restrict__ pulse, int T, int P,
                       float *__restrict__ out)
 {
-    __shared__ float win[kMfOut + kMfTaps];
-    __shared__ float taps[kMfTaps];
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    __shared__ float win[kMfWinSkewed];
+    __shared__ float tap[kMfTapTab];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWaveSize - 1);
+    const int wave = tid / kWaveSize;
     const int t0 = blockIdx.x * kMfOut;
     const size_t chan = (size_t)blockIdx.y * (size_t)T;
-    const int tid = threadIdx.x;
-    float acc = 0.0f;
+    const int g = lane >> 4, c = lane & 15;
+
+    v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = 0; k0 < P; k0 += kMfTaps) {
         const int np = min(kMfTaps, P - k0);
-        __syncthreads();
-        for (int i = tid; i < kMfOut + np - 1; i += kMfOut) {
+        const int ks = (np + 15 + 3) / 4;               // K steps: m < np + 15
+        const int wlen = kMfOut + 4 * ks;               // window indices read: < 1008 + 4 ks
+        __syncthreads();                                // previous piece's reads done
+        for (int i = tid; i < wlen; i += kMfWaves * kWaveSize) {
             const int t = t0 + k0 + i;
-            win[i] = t < T ? raw[chan + t] : 0.0f;
+            win[i + (i >> 4)] = t < T ? raw[chan + t] : 0.0f;
         }
-        for (int i = tid; i < np; i += kMfOut) taps[i] = pulse[k0 + i];
+        for (int i = tid; i < kMfLead + 4 * ks + 4; i += kMfWaves * kWaveSize) {
+            const int k = i - kMfLead;
+            tap[i] = (k >= 0 && k < np) ? pulse[k0 + k] : 0.0f;
+        }
         __syncthreads();
-        for (int k = 0; k < np; ++k) acc = __builtin_fmaf(win[tid + k], taps[k], acc);
+        // G[c][4kk + g] = tap[4kk + g - c]; R[4kk + g][c] = window[256 wave + 16c + g + 4kk]
+        const float *pa = tap + kMfLead + g - c;
+        const float *rb = win + 272 * wave + 17 * c + g;   // skewed index of 256 wave + 16c + g
+        int kk = 0;
+        for (; kk + 1 < ks; kk += 2) {
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)], e1,
+                                                      0, 0, 0);
+        }
+        if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
     }
-    const int t = t0 + tid;
-    if (t < T) out[chan + t] = acc;
+    const v4f e = e0 + e1;
+    const int t = t0 + kMfBlock * wave + 16 * c + 4 * g;   // a multiple of 4
+    float *dst = out + chan + t;
+    if (t + 3 < T && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+        *reinterpret_cast<v4f *>(dst) = e;
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (t + v < T) dst[v] = e[v];
+    }
 }
 
 }  // namespace
@@ -46,7 +93,7 @@ hipError_t launch_matched_filter(const float *raw, const float *pulse, int M, in
                                  hipStream_t stream)
 {
     const dim3 grid((unsigned)((T + kMfOut - 1) / kMfOut), (unsigned)M);
-    hipLaunchKernelGGL(matched_filter_kernel, grid, dim3(kMfOut), 0, stream, raw, pulse, T, P, out);
+    hipLaunchKernelGGL(matched_filter_kernel, grid, dim3(kMfWaves * kWaveSize), 0, stream, raw, pulse, T, P, out);
     return hipGetLastError();
 }
 

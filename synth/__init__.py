@@ -282,18 +282,19 @@ def echo_frame(rng: np.random.Generator, mics: np.ndarray, dirs: np.ndarray, T: 
                  truth=dict(reflectors=refl, pulse_len=pulse.size, sigma=sigma, pulse=pulse))
 
 
-def config2(seed_salt: int = 0, order: int = 5, num_samples: int = 16384) -> Frame:
+def config2(seed_salt: int = 0, order: int = 5, num_samples: int = 16384, matched: bool = True) -> Frame:
     """eRTIS-like pulse-echo frame: 32 mics, 91 x 46 az/el grid, 16384 samples at 450 kHz.
 
     32 microphones uniform in a 12 cm disc with 4 mm minimum spacing; azimuth
     -90..90 deg and elevation -45..45 deg in 2 deg steps (azimuth fastest);
     25-75 kHz linear chirp of 1 ms; 20 reflectors at 0.3-5 m with 1/r^2
-    amplitude; 20 dB SNR; matched filtered.
+    amplitude; 20 dB SNR; matched filtered (``matched=False``: the raw
+    channels of the same scene, the chirp in ``truth["pulse"]``).
     """
     rng = rng_for(2, seed_salt)
     mics = disc_array(rng, 32, 0.12, min_spacing=0.004)
     dirs = az_el_grid(np.arange(-90.0, 90.0 + 1e-9, 2.0), np.arange(-45.0, 45.0 + 1e-9, 2.0))
-    return echo_frame(rng, mics, dirs, num_samples, 20, order, name="config2")
+    return echo_frame(rng, mics, dirs, num_samples, 20, order, name="config2", apply_matched_filter=matched)
 
 
 def config3(seed_salt: int = 0, order: int = 5) -> Frame:

@@ -17,3 +17,15 @@ def test_algorithmic_slot_counts():
     assert bench.pixel_slots(32, 5, True, 63) == 309
     D, T, M = 4186, 16384, 32
     assert bench.launch_slots(M, T, D, 5, True, 63) == D * T * 309 + M * T * 6
+
+
+def test_linear_delay_slot_count():
+    # linear delays: per microphone the interpolation (2) and the root of the interpolated value (6)
+    # on top of the powers and sums: 32 * (2 + 6 + 7) + 15 + 6 + 1 + 63
+    assert bench.linear_pixel_slots(32, 5, True, 63) == 32 * 15 + 85
+
+
+def test_unknown_workload_is_rejected(capsys):
+    import pytest
+    with pytest.raises(SystemExit):
+        bench.main(["--workload", "nope"])
