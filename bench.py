@@ -284,7 +284,7 @@ def bench_linear(args) -> dict:
         out = torch.empty((D, T), dtype=torch.float32, device="cuda")
         stream = torch.cuda.current_stream()
         steps = max(5, args.steps // 5)
-        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, max(2, args.warmup // 5), stream)
+        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, args.warmup, stream)
         info = plan.info()
     pixels = D * T
     rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
@@ -322,7 +322,7 @@ def bench_pipeline(args) -> dict:
             plan.envelope(x, out=out)
 
         steps = max(5, args.steps // 5)
-        ms_per_step, step_ms = _timed(step, steps, max(2, args.warmup // 5), stream)
+        ms_per_step, step_ms = _timed(step, steps, args.warmup, stream)
         mf_ms = _timed(lambda: plan.matched_filter(raw, out=x), steps, 2, stream)[1]
         env_ms = _timed(lambda: plan.envelope(x, out=out), steps, 2, stream)[1]
         info = plan.info()

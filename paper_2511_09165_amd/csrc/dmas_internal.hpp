@@ -84,14 +84,15 @@ __host__ __device__ constexpr int env_prefix(int H) { return H + env_lead(H); }
 
 // Envelope LDS of a workgroup (floats), after the windows and reference
 // delays: a taps table of env_taps_len(H) floats (kTapLead zeros, the L =
-// 2H + 1 taps, zeros), then one ring per wave of ring_stride(H) floats. The
+// 2H + 1 taps in reverse order, zeros), then one ring per wave of
+// ring_stride(H) floats. The
 // ring holds |y| for ring index i in [0, env_prefix(H) + kChunk) at float
 // i + i / 16; the skew keeps the FIR's matrix-operand reads (16 indices 16
 // apart) on distinct LDS banks. The FIR is a product with K = 2H + 16 in steps
 // of 4 and reads ring indices up to 2H + kChunk + 2 (zero beyond the chunk).
 constexpr int kTapLead = 20;
 __host__ __device__ constexpr int env_ksteps(int H) { return (2 * H + 16 + 3) / 4; }
-__host__ __device__ constexpr int env_taps_len(int H) { return (kTapLead + 2 * H + 1 + 16 + 3) & ~3; }
+__host__ __device__ constexpr int env_taps_len(int H) { return (kTapLead + 2 * H + 24) & ~3; }
 __host__ __device__ constexpr int ring_logical(int H)
 {
     return kChunk + (env_prefix(H) > 2 * H + 8 ? env_prefix(H) : 2 * H + 8);

@@ -544,8 +544,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     if constexpr (ENV) {
         for (int i = lane; i < ring_stride(H); i += kWaveSize) ring[i] = 0.0f;
         for (int j = threadIdx.x; j < env_taps_len(H); j += W * kWaveSize) {
-            const int k = j - kTapLead;
-            tap_lds[j] = (k >= 0 && k < p.fir_len) ? taps[k] : 0.0f;
+            const int k = j - kTapLead;   // reversed: entry kTapLead + k holds h[2H - k]
+            tap_lds[j] = (k >= 0 && k <= 2 * H) ? taps[2 * H - k] : 0.0f;
         }
         // the first block's barrier makes the taps table visible before any epilogue
     }
@@ -559,8 +559,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         // env[t] for t = tc - lead + o, o in [0, C): sum_k h[k] |y[t + H - k]|
         //   = sum_k h[k] r[2H + o - k], r = the ring (r[i] = |y[tc - H - lead + i]|).
         // With o = 16j + i (i, j < 16) this is the 16 x 16 matrix product
-        //   F[i][j] = sum_m G[i][m] R[m][j],  G[i][m] = h[i + 2H - m] (zero
-        //   outside the taps),  R[m][j] = r[16j + m],  m < 2H + 16,
+        //   F[i][j] = sum_m G[i][m] R[m][j],  G[i][m] = h[i + 2H - m] = hr[m - i]
+        //   (hr = the taps reversed, zero outside),  R[m][j] = r[16j + m],
+        //   m < 2H + 16,
         // done on the matrix cores in FP32, K = 4 per step: lane l holds
         // G[l % 16][4kk + l / 16] and R[4kk + l / 16][l % 16] and receives
         // F[4 (l / 16) + v][l % 16], v < 4, i.e. the four consecutive
@@ -569,16 +570,28 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         typedef float v4f __attribute__((ext_vector_type(4)));
         const int g = lane >> 4, c = lane & 15;
         const float *rb = ring + 17 * c + g;                  // r[16c + g], skewed
-        const float *ha = tap_lds + kTapLead + c + 2 * H - g; // h[c + 2H - g]
+        const float *ha = tap_lds + kTapLead + g - c;         // hr[g - c]
         const int ks = env_ksteps(H);
         v4f e0 = {0.0f, 0.0f, 0.0f, 0.0f}, e1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        // K step kk = 4q + u reads the taps at ha[4kk] = hq[4u] (hq = ha + 16q) and
+        // the ring at rb[4kk + kk/4] = rq[4u] (rq = rb + 17q): in groups of four
+        // the eight reads use immediate offsets and are issued together. Even
+        // steps go to e0, odd ones to e1.
+        const float *hq = ha, *rq = rb;
         int kk = 0;
-        for (; kk + 1 < ks; kk += 2) {
-            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
-            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)],
-                                                      e1, 0, 0, 0);
+        for (; kk + 3 < ks; kk += 4, hq += 16, rq += 17) {
+            const float a0 = hq[0], a1 = hq[4], a2 = hq[8], a3 = hq[12];
+            const float b0 = rq[0], b1 = rq[4], b2 = rq[8], b3 = rq[12];
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, e1, 0, 0, 0);
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b3, e1, 0, 0, 0);
         }
-        if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[-4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+        for (; kk < ks; ++kk) {
+            const float a = ha[4 * kk], b = rb[4 * kk + (kk >> 2)];
+            if (kk & 1) e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, e1, 0, 0, 0);
+            else e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, e0, 0, 0, 0);
+        }
         const v4f e = e0 + e1;
         const int t0 = tc - lead + 16 * c + 4 * g;   // a multiple of 4 (tc - lead is one of 32)
         if (p.env_decim == 1) {

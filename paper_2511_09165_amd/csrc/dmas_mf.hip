@@ -67,13 +67,23 @@ matched_filter_kernel(const float *__restrict__ raw, const float *__restrict__ p
         // G[c][4kk + g] = tap[4kk + g - c]; R[4kk + g][c] = window[256 wave + 16c + g + 4kk]
         const float *pa = tap + kMfLead + g - c;
         const float *rb = win + 272 * wave + 17 * c + g;   // skewed index of 256 wave + 16c + g
+        // step kk = 4q + u: pa[4kk] = pq[4u] (pq = pa + 16q), rb[4kk + kk/4] = rq[4u]
+        // (rq = rb + 17q); groups of four issue their eight reads together
+        const float *pq = pa, *rq = rb;
         int kk = 0;
-        for (; kk + 1 < ks; kk += 2) {
-            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
-            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[4 * (kk + 1)], rb[4 * (kk + 1) + ((kk + 1) >> 2)], e1,
-                                                      0, 0, 0);
+        for (; kk + 3 < ks; kk += 4, pq += 16, rq += 17) {
+            const float a0 = pq[0], a1 = pq[4], a2 = pq[8], a3 = pq[12];
+            const float b0 = rq[0], b1 = rq[4], b2 = rq[8], b3 = rq[12];
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, e1, 0, 0, 0);
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b3, e1, 0, 0, 0);
         }
-        if (kk < ks) e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[4 * kk], rb[4 * kk + (kk >> 2)], e0, 0, 0, 0);
+        for (; kk < ks; ++kk) {
+            const float a = pa[4 * kk], b = rb[4 * kk + (kk >> 2)];
+            if (kk & 1) e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, e1, 0, 0, 0);
+            else e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, e0, 0, 0, 0);
+        }
     }
     const v4f e = e0 + e1;
     const int t = t0 + kMfBlock * wave + 16 * c + 4 * g;   // a multiple of 4

@@ -226,6 +226,35 @@ def test_config5_full_size_sampled_rows():
     _say(f"config5 {res}")
 
 
+def test_config2_linear_full_size_sampled_rows():
+    """The eRTIS-like frame with linear fractional delays (bench.py --workload linear); sampled rows."""
+    f = synth.config2()
+    rows = _sample_rows(f, 12, 7)
+    _say(f"config2 linear full size, rows {rows[:4]}...")
+    res = _compare(f, f.x_f32(), rows=rows, interp=True, t2=False)
+    _say(f"config2 linear {res}")
+
+
+def test_pipeline_full_size_sampled_rows():
+    """Raw eRTIS-like frame -> matched filter -> order-5 DMAS+CF -> envelope every 20th sample
+    (bench.py --workload pipeline) against the same chain in the oracle on sampled rows."""
+    f = synth.config2(matched=False)
+    pulse = f.truth["pulse"].astype(np.float32)
+    raw32 = f.x_f32()
+    taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32)
+    rows = _sample_rows(f, 12, 8)
+    _say(f"pipeline full size, rows {rows[:4]}...")
+    with _plan(f, mf_pulse=pulse, fir_taps=taps, env_decimation=20) as plan:
+        x = plan.matched_filter(torch.from_numpy(raw32).cuda())
+        env = plan.envelope(x)
+        torch.cuda.synchronize()
+        env = env[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
+    x_ref = oracle.matched_filter(raw32.astype(np.float64), pulse.astype(np.float64))
+    env_ref = oracle.envelope(oracle.frame_rows(f, x=x_ref, rows=rows), taps.astype(np.float64))[:, ::20]
+    assert env.shape == env_ref.shape
+    _say(f"pipeline t1 {check_t1(env, env_ref):.3g}")
+
+
 # ---------------------------------------------------------------------------
 # Invariants (bitwise)
 # ---------------------------------------------------------------------------
