@@ -654,12 +654,15 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // (whole-sample delays, n >= 2), else samples.
     const size_t elem = p->roots ? 2 * sizeof(float) : sizeof(float);
     auto lds_for = [&](int m) { return fixed + ring_bytes + elem * (size_t)m * p->row; };
-    const int mb_max = std::min(M, dmas::kMaxMicBlock);
     // Per-tile delay tables for whole-sample delays, when of modest size (the
     // delay mode selects the kernel, so it is fixed before the occupancy
     // queries below).
     const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
     p->tables = !p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE");
+    // with more microphones than lanes the kernel reads a block's offsets as one
+    // scalar block of lane_block_max(n) entries: that caps the block
+    const bool lane_tables = dmas::shape_of(p, true).delay == dmas::kDelayTableLanes;
+    const int mb_cap = lane_tables ? dmas::lane_block_max(n) : dmas::kMaxMicBlock;
     // Microphones per LDS block, from the envelope kernel's occupancy (its
     // registers, LDS and the wave limit decide): with M <= 64 the largest
     // block that keeps three workgroups per CU (or as many as any block
@@ -668,6 +671,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // (measured: 1024 microphones at order 3 run 7 % faster with 12-microphone
     // blocks at four workgroups per CU than with 16 at three, while 32
     // microphones run 5 % slower that way).
+    const int mb_max = std::min(M, mb_cap);
     const int occ_target = M <= dmas::kWaveSize ? 3 : 1 << 30;
     int mb = 0, best_occ = 0;
     for (int cand : {mb_max, 48, 32, 24, 16, 12, 8, 4, 2, 1}) {
@@ -704,7 +708,9 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // results between lanes.
     if (p->tables) {
         const size_t n_off = (size_t)p->num_tiles * W * M, n_dref = (size_t)p->num_tiles * M;
-        e = hipMalloc((void **)&p->d_tile_off, sizeof(int32_t) * n_off);
+        // kLaneBlockMax spare entries: a scalar block read may run past the last row
+        e = hipMalloc((void **)&p->d_tile_off, sizeof(int32_t) * (n_off + dmas::kLaneBlockMax));
+        if (e == hipSuccess) e = hipMemset(p->d_tile_off + n_off, 0, sizeof(int32_t) * dmas::kLaneBlockMax);
         if (e == hipSuccess) e = hipMalloc((void **)&p->d_tile_dref, sizeof(int32_t) * n_dref);
         if (e == hipSuccess) {
             auto kern = p->nearfield ? tile_table_kernel<true> : tile_table_kernel<false>;

@@ -11,6 +11,11 @@ namespace dmas {
 constexpr int kWaveSize = 64;
 constexpr int kMaxOrder = 8;
 constexpr int kMaxMicBlock = 64;   // microphones staged in LDS at once (<= wave size)
+// Microphones per block with kDelayTableLanes (a block's offsets are read as
+// one scalar block into SGPRs): 12 for orders up to 3, whose kernels have the
+// SGPR budget of eight waves per SIMD, else 16.
+__host__ __device__ constexpr int lane_block_max(int order) { return order <= 3 ? 12 : 16; }
+constexpr int kLaneBlockMax = 16;  // the largest, for padding the tables
 
 // Everything a beamforming launch needs, passed by value as the kernel argument.
 struct KernelParams {
@@ -63,9 +68,11 @@ struct LaunchShape {
 
 // How a kernel obtains its steering delays: evaluated on the device (whole
 // samples), evaluated with linear interpolation, or from the plan's per-tile
-// tables (whole samples), read through the scalar cache (small tables) or
-// per lane ahead of each microphone block (large tables, which would thrash
-// the scalar cache).
+// tables (whole samples). With at most 64 microphones the hot loop reads each
+// microphone's offset through the scalar cache one ahead of use; with more
+// (kDelayTableLanes) each wave reads its block's offsets as one scalar block
+// before the block's barrier and the reference delays per lane (per-microphone
+// scalar reads of a large table left their latency in the hot loop).
 enum : int { kDelayComputed = 0, kDelayLinear = 1, kDelayTable = 2, kDelayTableLanes = 3 };
 
 // Compile-time tiling shared by host and device: waves (= directions) per

@@ -423,7 +423,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 {
     constexpr bool LINEAR = DM == kDelayLinear;
     constexpr bool TAB = DM == kDelayTable;          // tables through the scalar cache
-    constexpr bool TAB_LANES = DM == kDelayTableLanes; // tables loaded per lane
+    constexpr bool TAB_LANES = DM == kDelayTableLanes; // offsets per block, references per lane
     constexpr int W = kDirsPerTile;
     constexpr int K = kSamplesPerLane;
     constexpr int C = kChunk;
@@ -466,7 +466,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     //    direction, microphone) and reference delays per (tile, microphone),
     //    read through the scalar cache (constant address space: the tables
     //    do not change while a kernel runs), so the per-microphone LDS
-    //    address of the hot loop costs one vector add;
+    //    address of the hot loop costs one vector add. With M <= 64 the hot
+    //    loop reads each offset one microphone ahead; with more microphones
+    //    (TAB_LANES) a wave reads its block's offsets as one scalar block
+    //    before the block's barrier and each lane its microphone's reference
+    //    delay;
     //  * M <= 64 without tables (linear delays): lane i of every wave computes
     //    its direction's delay for microphone i once, and wave 0 (the tile's
     //    reference direction) publishes its delays in LDS for the staging step;
@@ -484,6 +488,12 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                                       reinterpret_cast<uintptr_t>(p.tile_dref + (size_t)tile * p.M))
                                 : nullptr;
     const int32_t *off_lanes = TAB_LANES ? p.tile_off + ((size_t)tile * W + wave) * p.M : nullptr;
+    // lane-loaded tables: the block's window offsets of this wave's direction,
+    // loaded as one scalar block before the block's barrier (mic_block <= 16;
+    // the table is padded so that the 16-entry read stays inside it)
+    const_i32 *off_srow = TAB_LANES ? reinterpret_cast<const_i32 *>(reinterpret_cast<uintptr_t>(off_lanes)) : nullptr;
+    constexpr int LB = lane_block_max(N);
+    int soff[LB];
     const int32_t *dref_lanes = TAB_LANES ? p.tile_dref + (size_t)tile * p.M : nullptr;
     int mydref = 0;           // reference delay of microphone `lane` of the block (TAB_LANES)
     int mydw = 0;
@@ -495,10 +505,10 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         const int mic = blk * p.mic_block + lane;
         if constexpr (TAB_LANES) {
             // issued before the block's barrier so the loads overlap the wait
-            if (lane < p.mic_block && mic < p.M) {
-                myoff = off_lanes[mic];
-                mydref = dref_lanes[mic];
-            }
+            if (lane < p.mic_block && mic < p.M) mydref = dref_lanes[mic];
+            const_i32 *ob = off_srow + blk * p.mic_block;
+#pragma unroll
+            for (int k = 0; k < LB; ++k) soff[k] = ob[k];
             return;
         }
         const int nlanes = all_mics ? p.M : p.mic_block;
@@ -699,6 +709,10 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                         if (i + 1 < nm) o_next = ob[i + 1];
                         mic_step(i, o);
                     }
+                } else if constexpr (TAB_LANES) {
+#pragma unroll
+                    for (int i = 0; i < LB; ++i)
+                        if (i < nm) mic_step(i, soff[i]);
                 } else {
                     for (int i = 0; i < nm; ++i) mic_step(i, __builtin_amdgcn_readlane(myoff, i));
                 }
