@@ -199,7 +199,7 @@ def bench_headline(args) -> dict:
     import synth
     from paper_2511_09165_amd import plan_for_frame
 
-    frame = synth.config2()
+    frame = synth.ertis_frame()
     M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
     fir_len = 63
     plan = plan_for_frame(frame, fir_len=fir_len)
@@ -208,7 +208,7 @@ def bench_headline(args) -> dict:
     stream = torch.cuda.current_stream()
     ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), args.steps, args.warmup, stream)
     pixels = D * T
-    workload_key = f"config2 M={M} D={D} T={T} n={n} cf=1 env L={fir_len}"
+    workload_key = f"ertis32 M={M} D={D} T={T} n={n} cf=1 env L={fir_len}"
     rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
         "workload": "eRTIS-like frame: order-5 DMAS+CF+envelope, M=32 mics (12 cm sparse disc), "
                     "91x46 az/el directions, T=16384 samples at 450 kHz, 63-tap envelope FIR",
@@ -240,7 +240,7 @@ def bench_nearfield(args) -> dict:
     import synth
     from paper_2511_09165_amd import plan_for_frame
 
-    frame = synth.config5()
+    frame = synth.nearfield_frame()
     M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
     fir_len = 63
     with plan_for_frame(frame, fir_len=fir_len) as plan:
@@ -276,7 +276,7 @@ def bench_linear(args) -> dict:
     import synth
     from paper_2511_09165_amd import plan_for_frame
 
-    frame = synth.config2()
+    frame = synth.ertis_frame()
     M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
     fir_len = 63
     with plan_for_frame(frame, fir_len=fir_len, linear=True) as plan:
@@ -306,7 +306,7 @@ def bench_pipeline(args) -> dict:
     import synth
     from paper_2511_09165_amd import plan_for_frame
 
-    frame = synth.config2(matched=False)
+    frame = synth.ertis_frame(matched=False)
     M, D, T, n = frame.num_mics, frame.num_dirs, frame.num_samples, frame.order
     fir_len, decim = 63, 20
     pulse = frame.truth["pulse"].astype(np.float32)
@@ -353,7 +353,7 @@ def bench_precision(args) -> list:
     import synth
     from paper_2511_09165_amd import plan_for_frame
 
-    base = synth.config2()
+    base = synth.ertis_frame()
     D, T, M = base.num_dirs, base.num_samples, base.num_mics
     x32 = base.x_f32()
     amax = float(np.abs(x32).max())

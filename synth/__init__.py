@@ -61,8 +61,9 @@ class Frame:
         return np.ascontiguousarray(self.x.astype(np.float32))
 
 
-def rng_for(config: int, salt: int = 0) -> np.random.Generator:
-    return np.random.default_rng(SEED_BASE + config + 1000 * salt)
+def rng_for(stream: int, salt: int = 0) -> np.random.Generator:
+    """Seeded generator of workload ``stream`` (a fixed small integer per workload)."""
+    return np.random.default_rng(SEED_BASE + stream + 1000 * salt)
 
 
 # ----------------------------------------------------------------------------
@@ -216,7 +217,7 @@ def fractional_delay(sig: np.ndarray, delay_samples: float) -> np.ndarray:
 # Workloads
 # ----------------------------------------------------------------------------
 
-def config1(seed_salt: int = 0, order: int = 2) -> Frame:
+def burst_frame(seed_salt: int = 0, order: int = 2) -> Frame:
     """8 mics in a 5 cm disc, 64 azimuths over +-60 deg, 1024 samples at 450 kHz.
 
     Three point reflectors in the horizontal plane, each a Hann-windowed 40 kHz
@@ -243,7 +244,7 @@ def config1(seed_salt: int = 0, order: int = 2) -> Frame:
             x[i, s0:s0 + burst.size] += amp * burst
         refl.append(dict(az=az, el=0.0, amp=amp, onset=onset))
     x += rng.normal(0.0, 0.05, size=x.shape)
-    return Frame("config1", x, mics, dirs, fs, c, order, True, False,
+    return Frame("burst8", x, mics, dirs, fs, c, order, True, False,
                  truth=dict(reflectors=refl, pulse_len=burst.size))
 
 
@@ -282,7 +283,7 @@ def echo_frame(rng: np.random.Generator, mics: np.ndarray, dirs: np.ndarray, T: 
                  truth=dict(reflectors=refl, pulse_len=pulse.size, sigma=sigma, pulse=pulse))
 
 
-def config2(seed_salt: int = 0, order: int = 5, num_samples: int = 16384, matched: bool = True) -> Frame:
+def ertis_frame(seed_salt: int = 0, order: int = 5, num_samples: int = 16384, matched: bool = True) -> Frame:
     """eRTIS-like pulse-echo frame: 32 mics, 91 x 46 az/el grid, 16384 samples at 450 kHz.
 
     32 microphones uniform in a 12 cm disc with 4 mm minimum spacing; azimuth
@@ -294,13 +295,13 @@ def config2(seed_salt: int = 0, order: int = 5, num_samples: int = 16384, matche
     rng = rng_for(2, seed_salt)
     mics = disc_array(rng, 32, 0.12, min_spacing=0.004)
     dirs = az_el_grid(np.arange(-90.0, 90.0 + 1e-9, 2.0), np.arange(-45.0, 45.0 + 1e-9, 2.0))
-    return echo_frame(rng, mics, dirs, num_samples, 20, order, name="config2", apply_matched_filter=matched)
+    return echo_frame(rng, mics, dirs, num_samples, 20, order, name="ertis32", apply_matched_filter=matched)
 
 
-def config3(seed_salt: int = 0, order: int = 5) -> Frame:
-    """Mixed-precision sweep input: config 1's geometry and scene at a chosen order."""
-    f = config1(seed_salt, order=order)
-    f.name = "config3"
+def precision_frame(seed_salt: int = 0, order: int = 5) -> Frame:
+    """Mixed-precision sweep input: ``burst_frame``'s geometry and scene at a chosen order."""
+    f = burst_frame(seed_salt, order=order)
+    f.name = "precision_sweep"
     return f
 
 
@@ -339,7 +340,7 @@ def serving_pool(seed_salt: int = 0, n_arrays_per_m: int = 4, frames_per_combo: 
     return frames
 
 
-def config5(seed_salt: int = 0, order: int = 3, voxels=(64, 64, 32), num_samples: int = 2048) -> Frame:
+def nearfield_frame(seed_salt: int = 0, order: int = 3, voxels=(64, 64, 32), num_samples: int = 2048) -> Frame:
     """Near-field passive imaging: 32 x 32 grid (1 cm pitch), 64 x 64 x 32 voxels, 2048 samples at 192 kHz.
 
     Five broadband sources (unit-variance Gaussian noise band-limited to
@@ -366,7 +367,7 @@ def config5(seed_salt: int = 0, order: int = 3, voxels=(64, 64, 32), num_samples
         srcs.append(dict(pos=p))
     power = np.mean(sig ** 2, axis=1, keepdims=True)
     x = sig + rng.standard_normal(sig.shape) * np.sqrt(power)
-    return Frame("config5", x, mics, vox, fs, c, order, True, True, truth=dict(sources=srcs))
+    return Frame("nearfield1024", x, mics, vox, fs, c, order, True, True, truth=dict(sources=srcs))
 
 
 def random_frame(rng: np.random.Generator, M: int, D: int, T: int, order: int,

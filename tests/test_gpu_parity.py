@@ -64,14 +64,14 @@ def _compare(frame, x32, rows=None, check_env=True, taps=None, t2=True, interp=F
 # Steering delays: bit-exact
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("case", ["config2_far", "config5_near", "random_far_linear", "random_near_linear"])
+@pytest.mark.parametrize("case", ["ertis_far", "nearfield_near", "random_far_linear", "random_near_linear"])
 def test_steering_delays_bit_exact(case):
     _say(f"delays {case}")
-    if case == "config2_far":
-        f = synth.config2()
+    if case == "ertis_far":
+        f = synth.ertis_frame()
         linear = False
-    elif case == "config5_near":
-        f = synth.config5(voxels=(32, 32, 8))
+    elif case == "nearfield_near":
+        f = synth.nearfield_frame(voxels=(32, 32, 8))
         linear = False
     else:
         f = synth.random_frame(np.random.default_rng(3), 37, 300, 64, 3, nearfield=case.endswith("near_linear"))
@@ -115,12 +115,12 @@ def test_delays_at_rounding_ties():
 # Whole images at small sizes (several tiles, ragged tails)
 # ---------------------------------------------------------------------------
 
-def test_config1_parity():
+def test_burst_frame_parity():
     """Order-2 DMAS+CF, 8 mics, 64 azimuths, 1024 samples: every pixel, RF and envelope."""
-    f = synth.config1()
-    _say("config1 n=2 cf")
+    f = synth.burst_frame()
+    _say("burst frame n=2 cf")
     res = _compare(f, f.x_f32())
-    _say(f"config1 {res}")
+    _say(f"burst frame {res}")
 
 
 @pytest.mark.parametrize("nearfield", [False, True])
@@ -206,39 +206,39 @@ def _sample_rows(f, k, seed):
     return sorted(rows)
 
 
-def test_config2_full_size_sampled_rows():
+def test_ertis_frame_full_size_sampled_rows():
     """eRTIS-like frame: M=32, D=4186, T=16384, order 5 + CF; full launch, oracle on sampled rows."""
-    f = synth.config2()
+    f = synth.ertis_frame()
     rows = _sample_rows(f, 22, 5)
     # also the direction with the strongest DAS response (a bright pixel)
     das = oracle.dmas_rows(f.x, f.mic_pos, f.dirs, f.fs, f.c, 1, use_cf=False, rows=rows)
-    _say(f"config2 full size, rows {rows[:4]}...")
+    _say(f"eRTIS-like frame full size, rows {rows[:4]}...")
     res = _compare(f, f.x_f32(), rows=rows)
-    _say(f"config2 {res} (das peak {np.abs(das).max():.3g})")
+    _say(f"eRTIS-like frame {res} (das peak {np.abs(das).max():.3g})")
 
 
-def test_config5_full_size_sampled_rows():
+def test_nearfield_frame_full_size_sampled_rows():
     """Near field: M=1024 (16 LDS blocks), 64x64x32 voxels, T=2048, order 3 + CF; oracle on sampled rows."""
-    f = synth.config5()
+    f = synth.nearfield_frame()
     rows = _sample_rows(f, 10, 6)
-    _say(f"config5 full size, rows {rows[:4]}...")
+    _say(f"near-field frame full size, rows {rows[:4]}...")
     res = _compare(f, f.x_f32(), rows=rows, taps=oracle.lowpass_taps(63, 5000.0, f.fs))
-    _say(f"config5 {res}")
+    _say(f"near-field frame {res}")
 
 
-def test_config2_linear_full_size_sampled_rows():
+def test_ertis_frame_linear_full_size_sampled_rows():
     """The eRTIS-like frame with linear fractional delays (bench.py --workload linear); sampled rows."""
-    f = synth.config2()
+    f = synth.ertis_frame()
     rows = _sample_rows(f, 12, 7)
-    _say(f"config2 linear full size, rows {rows[:4]}...")
+    _say(f"eRTIS-like frame linear full size, rows {rows[:4]}...")
     res = _compare(f, f.x_f32(), rows=rows, interp=True, t2=False)
-    _say(f"config2 linear {res}")
+    _say(f"eRTIS-like frame linear {res}")
 
 
 def test_pipeline_full_size_sampled_rows():
     """Raw eRTIS-like frame -> matched filter -> order-5 DMAS+CF -> envelope every 20th sample
     (bench.py --workload pipeline) against the same chain in the oracle on sampled rows."""
-    f = synth.config2(matched=False)
+    f = synth.ertis_frame(matched=False)
     pulse = f.truth["pulse"].astype(np.float32)
     raw32 = f.x_f32()
     taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32)
@@ -303,7 +303,7 @@ def test_determinism_and_streams():
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
 def test_half_precision_storage(dtype):
     """FP16/BF16 channels with a per-frame scale: parity against the oracle on the dequantised values."""
-    f = synth.config3(order=5)
+    f = synth.precision_frame(order=5)
     tdt = torch.float16 if dtype == "f16" else torch.bfloat16
     amax = np.abs(f.x).max()
     scale = 2.0 ** np.floor(np.log2(amax / 16384.0)) if dtype == "f16" else 1.0
@@ -322,7 +322,7 @@ def test_half_precision_storage(dtype):
                                      dict(ng_fp64=True, compensated=True), dict(accumulate="f64")])
 @pytest.mark.parametrize("n", [2, 5, 7])
 def test_precision_variants(n, variant):
-    f = synth.config3(order=n)
+    f = synth.precision_frame(order=n)
     _say(f"precision n={n} {variant}")
     _compare(f, f.x_f32(), **variant)
 
@@ -394,7 +394,7 @@ def test_matched_filter_shapes(M, T, P):
 
 def test_matched_filter_full_frame_sampled():
     """The 32 x 16384 eRTIS-like raw frame with its 450-sample chirp: sampled channels vs the oracle."""
-    f = synth.config2()
+    f = synth.ertis_frame()
     pulse = synth.linear_chirp(f.fs, 25e3, 75e3, 1e-3).astype(np.float32)
     rng = np.random.default_rng(1100)
     raw32 = rng.normal(size=(f.num_mics, f.num_samples)).astype(np.float32)

@@ -48,7 +48,7 @@ def test_precision_sweep():
     from paper_2511_09165_amd import plan_for_frame
     table = []
     for n in (2, 3, 4, 5, 6, 7):
-        f = synth.config3(order=n)
+        f = synth.precision_frame(order=n)
         taps = oracle.lowpass_taps(63, 5000.0, f.fs)
         y_ref = oracle.frame_rows(f)                      # original FP64 data
         env_ref = oracle.envelope(y_ref, taps.astype(np.float32).astype(np.float64))
