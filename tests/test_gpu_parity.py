@@ -437,6 +437,18 @@ def test_envelope_decimation(k):
     check_t1(dec, env_ref[:, ::k])
 
 
+@pytest.mark.parametrize("T,k", [(700, 700), (700, 699), (33, 5), (1, 1), (2, 2), (300, 256)])
+def test_decimation_extremes(T, k):
+    """Decimation up to k = T (one kept sample per direction) and records shorter than the FIR:
+    the kept samples are the full-rate envelope's, bitwise."""
+    f = synth.random_frame(np.random.default_rng(700 + T + k), 6, 11, T, 3)
+    _say(f"decimation T={T} k={k}")
+    full = _run(f, f.x_f32(), env=True)
+    dec = _run(f, f.x_f32(), env=True, env_decimation=k)
+    assert dec.shape == (f.num_dirs, -(-T // k))
+    np.testing.assert_array_equal(dec, full[:, ::k])
+
+
 @pytest.mark.parametrize("T", [1000, 997])
 @pytest.mark.parametrize("L", [1, 3, 5, 7, 9, 61, 63, 65, 127, 255])
 def test_envelope_fir_lengths(L, T):
