@@ -14,6 +14,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/dmas.h"
@@ -179,62 +180,73 @@ void plan_free(dmas_plan_s *p)
     delete p;
 }
 
-// Chunks of samples that the longest of the segments of length s walks. The
-// kernels compute the samples [max(g0 - lead, 0), min(g1 + H, T)) of segment
-// [g0, g1), lead = H rounded up to a multiple of 32 (H = 0 without the
-// envelope). Segments that start at or after `lead` and end at least H before
-// T all walk the same count, so the first few and the last two decide.
-int segment_chunks(int T, int H, int s)
+// Launch time, in chunk-times, of segments of length s: workgroups go in
+// launch order (tiles fastest, then segments) to whichever of the `slots`
+// resident places frees first, and a workgroup of segment k takes its
+// chunks plus kWorkgroupSetup. All workgroups of a segment take equally
+// long, so the places' free times are kept as (time, count) pairs.
+constexpr double kWorkgroupSetup = 0.5;   // fixed cost per workgroup, in chunk-times (measured fit)
+
+double launch_makespan(int T, int H, int s, int num_tiles, int64_t slots, int64_t *total_chunks)
 {
     const int C = dmas::kChunk, lead = dmas::env_lead(H);
-    const int n = (T + s - 1) / s;
-    int worst = 0;
-    auto walk = [&](int k) {
-        const int g0 = k * s, g1 = std::min(g0 + s, T);
-        worst = std::max(worst, (std::min(g1 + H, T) - std::max(g0 - lead, 0) + C - 1) / C);
-    };
-    for (int k = 0; k < std::min(n, lead / 32 + 2); ++k) walk(k);
-    for (int k = std::max(0, n - 2); k < n; ++k) walk(k);
-    return worst;
+    std::map<double, int64_t> free_at{{0.0, slots}};
+    int64_t chunks = 0;
+    for (int g0 = 0; g0 < T; g0 += s) {
+        const int g1 = std::min(g0 + s, T);
+        const int c = (std::min(g1 + H, T) - std::max(g0 - lead, 0) + C - 1) / C;
+        chunks += c;
+        const double d = c + kWorkgroupSetup;
+        // the earliest free places take the next workgroups; a place whose
+        // workgroup ends can take another of the same segment (d > 0)
+        for (int64_t need = num_tiles; need > 0;) {
+            const auto it = free_at.begin();
+            const double t = it->first;
+            const int64_t m = std::min(it->second, need);
+            if ((it->second -= m) == 0) free_at.erase(it);
+            free_at[t + d] += m;
+            need -= m;
+        }
+    }
+    *total_chunks = chunks * num_tiles;
+    return free_at.rbegin()->first;
 }
 
 // Output samples per workgroup. Every segment is a multiple of 32 samples
 // (aligned output lines); a segment away from the record's ends walks
 // s + H + lead samples, and s is the longest that keeps that walk's chunk
-// count. The count is chosen to minimise (workgroup rounds on the device) x
-// (chunks per workgroup): long segments waste little halo, but the last round
-// of workgroups should not leave most CUs idle.
+// count. The count minimises the launch's makespan (above): long segments
+// recompute little halo and pay the workgroup setup less often, but the last
+// workgroups should not leave most of the device idle. Ties go to less work.
 void choose_segments(int T, int num_tiles, int H, int64_t slots, int fixed, int *seg, int *nseg)
 {
     const int C = dmas::kChunk;
     const int extra = H + dmas::env_lead(H);
-    auto shape = [&](int want, int *s_out, int *n_out, int *chunks_out) {
-        int s = ((T + want - 1) / want + 31) & ~31;
-        const int chunks = (s + extra + C - 1) / C;
-        s = std::max(32, (chunks * C - extra) & ~31);
-        *s_out = s;
-        *n_out = (T + s - 1) / s;
-        *chunks_out = segment_chunks(T, H, s);
-    };
     if (fixed > 0) {
         *seg = (fixed + 31) & ~31;
         *nseg = (T + *seg - 1) / *seg;
         return;
     }
     double best = 0;
+    int64_t best_work = 0;
+    int last_s = -1;
     const int max_seg = std::max(1, (T + 31) / 32);
     for (int want = 1; want <= max_seg; ++want) {
-        int s, nsg, chunks;
-        shape(want, &s, &nsg, &chunks);
-        const int64_t wgs = (int64_t)num_tiles * nsg;
-        const double rounds = (double)((wgs + slots - 1) / slots);
-        const double cost = rounds * chunks;
-        if (want == 1 || cost < best * (1.0 - 1e-9)) {
+        int s = ((T + want - 1) / want + 31) & ~31;
+        const int chunks = (s + extra + C - 1) / C;
+        s = std::max(32, (chunks * C - extra) & ~31);
+        if (s == last_s) continue;
+        last_s = s;
+        const int nsg = (T + s - 1) / s;
+        int64_t work = 0;
+        const double cost = launch_makespan(T, H, s, num_tiles, slots, &work);
+        if (want == 1 || cost < best * (1.0 - 1e-9) || (cost <= best * (1.0 + 1e-9) && work < best_work)) {
             best = cost;
+            best_work = work;
             *seg = s;
             *nseg = nsg;
         }
-        if (wgs > 64 * slots) break;
+        if ((int64_t)num_tiles * nsg > 64 * slots) break;
     }
 }
 
