@@ -22,6 +22,7 @@ import gc
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -75,12 +76,21 @@ def launch_slots(M: int, T: int, D: int, n: int, cf: bool, fir_len: int) -> int:
     return D * T * pixel_slots(M, n, cf, fir_len) + M * T * root_slots(n)
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and with whitespace runs collapsed (what the compiler sees)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the code (comments and layout ignored) that the headline kernel is built from; the
+    committed HBM counter record applies only while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_09165_amd", "csrc")
     for name in ("dmas_api.hip", "dmas_internal.hpp", "dmas_kernel.hpp", "dmas_order5.hip"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update((name + _code_only(f.read())).encode())
     return h.hexdigest()[:16]
 
 

@@ -488,7 +488,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                                       reinterpret_cast<uintptr_t>(p.tile_dref + (size_t)tile * p.M))
                                 : nullptr;
     const int32_t *off_lanes = TAB_LANES ? p.tile_off + ((size_t)tile * W + wave) * p.M : nullptr;
-    // lane-loaded tables: the block's window offsets of this wave's direction,
+    // tables for more than 64 microphones: the block's window offsets of this wave's direction,
     // loaded as one scalar block before the block's barrier (mic_block <= 16;
     // the table is padded so that the 16-entry read stays inside it)
     const_i32 *off_srow = TAB_LANES ? reinterpret_cast<const_i32 *>(reinterpret_cast<uintptr_t>(off_lanes)) : nullptr;
@@ -754,7 +754,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 // Register budget: the kernel is compiled for kMinWavesPerSimd waves per SIMD
 // (512 / waves VGPRs; a workgroup puts two waves on each SIMD).
 //  * 8 (64 VGPRs): orders up to 3 with FP32 sums fit it, SGPRs included. With
-//    more than 64 microphones (lane-loaded delay tables) that lets four
+//    more than 64 microphones (delay tables read per block) that lets four
 //    workgroups share a CU (measured 8 % faster on the 1024-microphone
 //    near-field frame); with fewer, LDS keeps the kernel at three workgroups
 //    anyway and the tighter budget only costs (2 % on a 32-microphone frame).
