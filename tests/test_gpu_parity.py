@@ -327,6 +327,28 @@ def test_precision_variants(n, variant):
     _compare(f, f.x_f32(), **variant)
 
 
+@pytest.mark.parametrize("dtype,variant", [("f32", dict(accumulate="f64")), ("f32", dict(compensated=True)),
+                                           ("f16", dict(ng_fp64=True)), ("bf16", dict())])
+def test_precision_forms_full_size_sampled_rows(dtype, variant):
+    """The precision forms at the eRTIS-like frame's full size, as bench.py --workload precision times
+    them (order 5, CF, envelope): oracle on sampled rows of the same (dequantised) channel values."""
+    f = synth.ertis_frame()
+    rows = _sample_rows(f, 8, 9)
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    amax = np.abs(f.x_f32()).max()
+    scale = 2.0 ** np.floor(np.log2(amax / 16384.0)) if dtype == "f16" else 1.0
+    xq = torch.from_numpy(f.x_f32() / np.float32(scale)).to(tdt)
+    x_deq = xq.float().numpy().astype(np.float64) * scale
+    taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32)
+    _say(f"precision full size {dtype} {variant}")
+    with _plan(f, in_dtype=dtype, fir_taps=taps, **variant) as plan:
+        env = plan.envelope(xq.cuda(), in_scale=scale)
+        torch.cuda.synchronize()
+        env = env[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
+    env_ref = oracle.envelope(oracle.frame_rows(f, x=x_deq, rows=rows), taps.astype(np.float64))
+    _say(f"precision full size {dtype} {variant} t1 {check_t1(env, env_ref):.3g}")
+
+
 @pytest.mark.parametrize("nearfield", [False, True])
 @pytest.mark.parametrize("n", [1, 3, 5])
 def test_linear_delays(n, nearfield):
