@@ -147,7 +147,13 @@ dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *desc);
  * tiling, and for whole-sample delays build per-tile delay tables on the
  * device (36 bytes per tile of 8 directions and microphone; skipped above
  * 2 GiB). Synchronises the null stream. On success *out receives the plan. n > M, an even fir_len and a
- * non-unit far-field direction (| |u| - 1 | > 1e-6) are DMAS_ERR_INVALID_ARG. */
+ * non-unit far-field direction (| |u| - 1 | > 1e-6) are DMAS_ERR_INVALID_ARG.
+ * Environment overrides read here (tuning and tests only; results do not
+ * depend on them beyond rounding order, which none of them changes):
+ * DMAS_SEGMENT=s fixes the samples per workgroup (rounded up to 32),
+ * DMAS_MIC_BLOCK=m the microphones per LDS block (clamped to the valid
+ * range), DMAS_NO_DELAY_TABLE evaluates the delays on the device instead of
+ * building tables, DMAS_LOG prints the plan's choices and errors to stderr. */
 dmas_status_t dmas_plan_create(const dmas_plan_desc_t *desc, dmas_plan_t *out);
 
 /* Release a plan and its device memory. NULL is a no-op. Work queued with
