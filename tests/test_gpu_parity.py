@@ -300,6 +300,36 @@ def test_determinism_and_streams():
 # Precision forms and linear delays
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("env", [False, True])
+def test_graph_capture_replays(env):
+    """dmas_beamform / dmas_envelope captured in a HIP graph (the root plane's stream-ordered pool
+    allocation, the root pass, the beamformer and the free): every replay, with eager work between
+    replays, gives the eager result bit for bit."""
+    f = synth.random_frame(np.random.default_rng(5), 16, 40, 700, 5)
+    _say(f"graph capture env={env}")
+    with _plan(f) as plan:
+        run = plan.envelope if env else plan.beamform
+        x = torch.from_numpy(f.x_f32()).cuda()
+        out = torch.empty((f.num_dirs, f.num_samples), device="cuda")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            run(x, out=out)
+            torch.cuda.synchronize()
+            ref = out.clone()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                run(x, out=out, stream=s)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref)
+            run(x, out=torch.empty_like(out))   # eager work between replays
+            torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
 def test_half_precision_storage(dtype):
     """FP16/BF16 channels with a per-frame scale: parity against the oracle on the dequantised values."""
