@@ -89,6 +89,32 @@ def test_batched_equals_alone_bitwise():
         p.close()
 
 
+def test_large_arrays_batched_bitwise():
+    """Frames of more than 64 microphones (delay offsets read per microphone block) in multi-frame
+    launches: the same bits as alone, next to frames of 64 or fewer microphones."""
+    from paper_2511_09165_amd import plan_for_frame
+    rng = np.random.default_rng(7)
+    frames = [_blocker()]
+    # runs of the same kernel class (order, geometry), which the server packs together
+    for M, n, near in [(100, 3, False), (150, 3, False), (72, 3, False), (130, 5, True), (100, 5, True),
+                       (32, 3, False)]:
+        # few directions and samples: frames that do not fill the device alone, so they are packed
+        f = synth.random_frame(rng, M, int(rng.integers(8, 24)), int(rng.choice([256, 300])), n,
+                               nearfield=near)
+        f.env = True
+        frames.append(f)
+    plans = [plan_for_frame(f) for f in frames]
+    alone = [_standalone(p, f.x_f32(), f.env) for f, p in zip(frames, plans)]
+    _say("serving: frames of 72-150 microphones, batching server")
+    outs, infos, stats = _run_server(frames, plans, hbm_budget=8 << 30, num_streams=2, max_batch=64)
+    for k, (a, b) in enumerate(zip(alone, outs)):
+        assert np.array_equal(a, b), f"frame {k} differs between alone and batched"
+    assert stats["completed"] == len(frames) and stats["failed"] == 0
+    assert max(i["batch_frames"] for i in infos[1:]) > 1, "no batching happened"
+    for p in plans:
+        p.close()
+
+
 def test_budget_limits_admission():
     """A budget that holds about two frames: every frame still completes, peak use stays within it."""
     from paper_2511_09165_amd import plan_for_frame
