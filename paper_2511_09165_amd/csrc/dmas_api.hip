@@ -169,14 +169,15 @@ void plan_free(dmas_plan_s *p)
     int cur = 0;
     bool switched = false;
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) switched = hipSetDevice(p->device) == hipSuccess;
-    hipFree(p->d_mic);
-    hipFree(p->d_dirs);
-    hipFree(p->d_tiles);
-    hipFree(p->d_tile_off);
-    hipFree(p->d_tile_dref);
-    hipFree(p->d_taps);
-    hipFree(p->d_pulse);
-    if (switched) hipSetDevice(cur);
+    // teardown: a failed free has no caller to report to
+    (void)hipFree(p->d_mic);
+    (void)hipFree(p->d_dirs);
+    (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_tile_off);
+    (void)hipFree(p->d_tile_dref);
+    (void)hipFree(p->d_taps);
+    (void)hipFree(p->d_pulse);
+    if (switched) (void)hipSetDevice(cur);
     delete p;
 }
 
@@ -643,7 +644,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         std::vector<int32_t> spread(p->num_tiles);
         if (e == hipSuccess)
             e = hipMemcpy(spread.data(), d_spread, sizeof(int32_t) * p->num_tiles, hipMemcpyDeviceToHost);
-        hipFree(d_spread);
+        (void)hipFree(d_spread);
         if (e != hipSuccess) {
             plan_free(p);
             return hip_fail(e, "tile spread");

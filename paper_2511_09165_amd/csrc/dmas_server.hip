@@ -464,8 +464,10 @@ struct dmas_server_s {
 
     void run()
     {
-        hipSetDevice(device);
         std::unique_lock<std::mutex> lk(mu);
+        // a failure here makes every later device call of this thread fail too,
+        // and those mark their frames failed
+        if (hipSetDevice(device) != hipSuccess) worker_error = "cannot select the server's device";
         while (!stop.load()) {
             bool progress = collect_completions();
             progress |= admit();
@@ -503,7 +505,10 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
     if (d->num_streams > 16) return srv_fail(DMAS_ERR_INVALID_ARG, "num_streams > 16");
     auto *s = new (std::nothrow) dmas_server_s();
     if (!s) return srv_fail(DMAS_ERR_OUT_OF_MEMORY, "host allocation failed");
-    hipGetDevice(&s->device);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return srv_fail(DMAS_ERR_DEVICE, "no current device");
+    }
     s->budget = align_up((size_t)d->hbm_budget_bytes);
     s->staging = align_up(d->staging_bytes ? (size_t)d->staging_bytes : (size_t)256 << 20);
     s->nstreams = d->num_streams ? d->num_streams : 2;
@@ -740,23 +745,24 @@ dmas_status_t dmas_server_destroy(dmas_server_t s)
         s->cv_work.notify_all();
         s->worker.join();
     }
+    // teardown: failures here have no caller to report to
     for (hipStream_t st : s->streams)
-        if (st) hipStreamSynchronize(st);
-    if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
+        if (st) (void)hipStreamSynchronize(st);
+    if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
     for (auto &kv : s->frames) {
-        if (kv.second->copied) hipEventDestroy(kv.second->copied);
+        if (kv.second->copied) (void)hipEventDestroy(kv.second->copied);
         delete kv.second;
     }
-    for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     for (auto &l : s->launches)
-        if (l.done) hipEventDestroy(l.done);
+        if (l.done) (void)hipEventDestroy(l.done);
     for (hipStream_t st : s->streams)
-        if (st) hipStreamDestroy(st);
-    if (s->copy_stream) hipStreamDestroy(s->copy_stream);
-    for (char *p : s->d_tables) hipFree(p);
-    for (char *p : s->h_tables) hipHostFree(p);
-    hipFree(s->d_arena);
-    hipHostFree(s->h_staging);
+        if (st) (void)hipStreamDestroy(st);
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    for (char *p : s->d_tables) (void)hipFree(p);
+    for (char *p : s->h_tables) (void)hipHostFree(p);
+    (void)hipFree(s->d_arena);
+    (void)hipHostFree(s->h_staging);
     delete s;
     return DMAS_OK;
 }
