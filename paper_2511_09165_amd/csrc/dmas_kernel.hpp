@@ -654,6 +654,10 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             __syncthreads();  // reference delays visible; previous block's reads done
             block_offsets(blk);
             // ---- stage this block's channel windows into LDS ----
+            // With many small blocks (more than 64 microphones) the waves issue
+            // their window loads at raised priority, so the loads go out early
+            // (0.9 % on the 1024-microphone frame; 0.4 % slower with 32).
+            if constexpr (TAB_LANES) __builtin_amdgcn_s_setprio(2);
             for (int i = wave; i < p.mic_block; i += W) {
                 const int mic = blk * p.mic_block + i;
                 Elem *dst = xwin + i * p.row;
@@ -671,6 +675,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                     for (int r = lane; r < p.row; r += kWaveSize) dst[r] = Elem{};
                 }
             }
+            if constexpr (TAB_LANES) __builtin_amdgcn_s_setprio(0);
             __syncthreads();
             // ---- hot loop: delayed samples -> roots -> power sums ----
             if (active) {
