@@ -247,6 +247,9 @@ class Plan:
                 or not x.is_contiguous():
             raise ValueError(f"x must be a contiguous {want} device tensor of shape "
                              f"({self.num_mics}, {self.num_samples}); got {x.dtype} {tuple(x.shape)}")
+        # the library checks that the current device is the plan's; the data must be there too
+        if x.device.index != torch.cuda.current_device():
+            raise ValueError(f"x is on {x.device} but device {torch.cuda.current_device()} is current")
 
     def _out(self, x, out, samples=None):
         import torch
@@ -282,8 +285,13 @@ class Plan:
         if not raw.is_cuda or raw.dtype != torch.float32 or tuple(raw.shape) != (self.num_mics, self.num_samples) \
                 or not raw.is_contiguous():
             raise ValueError("raw must be a contiguous float32 (M, T) device tensor")
+        if raw.device.index != torch.cuda.current_device():
+            raise ValueError(f"raw is on {raw.device} but device {torch.cuda.current_device()} is current")
         if out is None:
             out = torch.empty_like(raw)
+        elif out.dtype != torch.float32 or tuple(out.shape) != tuple(raw.shape) or not out.is_contiguous() \
+                or out.device != raw.device:
+            raise ValueError("out must be a contiguous float32 (M, T) tensor on raw's device")
         _check(self._lib.dmas_matched_filter(self._handle, ctypes.c_void_p(raw.data_ptr()),
                                              ctypes.c_void_p(out.data_ptr()),
                                              ctypes.c_void_p(_stream_handle(stream))))

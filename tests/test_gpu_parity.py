@@ -539,6 +539,23 @@ def test_envelope_segment_walks(L, T, seg, monkeypatch):
     np.testing.assert_array_equal(dec, env[:, ::5])
 
 
+def test_bad_output_buffers_rejected():
+    """Output tensors of the wrong shape, type, layout or device are refused before any launch."""
+    f = synth.random_frame(np.random.default_rng(97), 8, 5, 100, 2)
+    pulse = np.ones(7, dtype=np.float32)
+    with _plan(f, mf_pulse=pulse) as plan:
+        x = torch.zeros((8, 100), dtype=torch.float32, device="cuda")
+        for bad in (torch.zeros((8, 99), device="cuda"), torch.zeros((8, 100), dtype=torch.float64, device="cuda"),
+                    torch.zeros((100, 8), device="cuda").t(), torch.zeros((8, 100))):
+            with pytest.raises(ValueError):
+                plan.matched_filter(x, out=bad)
+        for bad in (torch.zeros((5, 99), device="cuda"), torch.zeros((5, 100), dtype=torch.float16, device="cuda")):
+            with pytest.raises(ValueError):
+                plan.beamform(x, out=bad)
+            with pytest.raises(ValueError):
+                plan.envelope(x, out=bad)
+
+
 def test_plan_rejects_bad_pipeline_options():
     from paper_2511_09165_amd import DmasError
     f = synth.random_frame(np.random.default_rng(96), 8, 5, 100, 2)
