@@ -283,7 +283,9 @@ dmas_status_t dmas_server_wait(dmas_server_t srv, uint64_t ticket, double timeou
 /* Return a done frame's device memory to the arena and forget the ticket. */
 dmas_status_t dmas_server_release(dmas_server_t srv, uint64_t ticket);
 
-/* Copy a done frame's result (D x T FP32) into host memory h_out (synchronous). */
+/* Copy a done frame's result into host memory h_out (synchronous): D x T FP32,
+ * or D x ceil(T/k) for an envelope of a plan with env_decimation k; h_out
+ * must hold that many floats. */
 dmas_status_t dmas_server_fetch(dmas_server_t srv, uint64_t ticket, float *h_out);
 
 /* Move up to max records of auto-released, completed frames into out

@@ -333,6 +333,7 @@ class Server:
         self._lib = load_library()
         d = ServerDesc(int(hbm_budget), int(staging), int(num_streams), int(max_batch))
         self._h = ctypes.c_void_p()
+        self._shapes = {}   # ticket -> result shape, for frames whose result stays on the device
         _check(self._lib.dmas_server_create(ctypes.byref(d), ctypes.byref(self._h)))
 
     def close(self) -> None:
@@ -365,6 +366,9 @@ class Server:
         _check(self._lib.dmas_server_submit(self._h, ctypes.c_void_p(plan.handle),
                                             xa.ctypes.data_as(ctypes.c_void_p), float(in_scale), flags,
                                             float(arrival), ctypes.byref(t)))
+        if not auto_release:
+            # the result's shape, for fetch: the library copies the whole result
+            self._shapes[int(t.value)] = (plan.num_dirs, plan.env_samples if envelope else plan.num_samples)
         return int(t.value)
 
     def query(self, ticket: int) -> dict:
@@ -377,13 +381,21 @@ class Server:
         _check(self._lib.dmas_server_wait(self._h, ticket, float(timeout), ctypes.byref(info)))
         return info.as_dict()
 
-    def fetch(self, ticket: int, shape) -> np.ndarray:
-        out = np.empty(shape, dtype=np.float32)
+    def fetch(self, ticket: int, shape=None) -> np.ndarray:
+        """The done frame's result as a (D, T) float32 array ((D, ceil(T / k)) for an envelope
+        decimated by k); ``shape``, if given, must be that shape."""
+        want = self._shapes.get(int(ticket))
+        if want is None:
+            raise ValueError(f"no result to fetch for ticket {ticket} (unknown, released or auto-released)")
+        if shape is not None and tuple(shape) != want:
+            raise ValueError(f"the result of ticket {ticket} has shape {want}, not {tuple(shape)}")
+        out = np.empty(want, dtype=np.float32)
         _check(self._lib.dmas_server_fetch(self._h, ticket, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def release(self, ticket: int) -> None:
         _check(self._lib.dmas_server_release(self._h, ticket))
+        self._shapes.pop(int(ticket), None)
 
     def completed(self, max_records: int = 4096) -> list:
         buf = (FrameInfo * max_records)()

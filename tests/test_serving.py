@@ -194,7 +194,12 @@ def test_rejections_and_release_rules():
         except DmasError as err:
             assert err.status == 5                    # DMAS_ERR_BUSY
         srv.wait(t1)
+        with pytest.raises(ValueError):
+            srv.fetch(t1, (100, 4095))                # not the result's shape (binding check)
+        assert srv.fetch(t1).shape == (100, 4096)     # the envelope's (D, T)
         srv.release(t1)
+        with pytest.raises(ValueError):
+            srv.fetch(t1)                             # released: nothing to fetch
         with pytest.raises(DmasError):
             srv.release(t1)                           # unknown ticket now
         with pytest.raises(DmasError):
