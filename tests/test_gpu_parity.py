@@ -539,6 +539,35 @@ def test_envelope_segment_walks(L, T, seg, monkeypatch):
     np.testing.assert_array_equal(dec, env[:, ::5])
 
 
+@pytest.mark.parametrize("seed", list(range(24)))
+def test_random_configurations(seed):
+    """Random combinations of the plan's options (sizes, order, CF, geometry, delay mode, accumulation,
+    FIR length, decimation) against the oracle: envelope within T1, and the RF image within T1."""
+    rng = np.random.default_rng(4000 + seed)
+    M = int(rng.integers(1, 100))
+    n = int(rng.integers(1, min(8, M) + 1))
+    near = bool(rng.random() < 0.3)
+    f = synth.random_frame(rng, M, int(rng.integers(1, 200)), int(rng.integers(1, 2500)), n, nearfield=near)
+    f.use_cf = bool(rng.random() < 0.8)
+    linear = bool(rng.random() < 0.2)
+    acc = "f32"
+    if f.use_cf and not near and not linear and rng.random() < 0.3:
+        acc = str(rng.choice(["kahan", "f64"]))
+    L = int(rng.choice([1, 3, 31, 63, 127]))
+    dec = int(rng.choice([1, 1, 1, 3, 8]))
+    taps = rng.normal(size=L).astype(np.float32)
+    _say(f"random #{seed}: M={M} D={f.num_dirs} T={f.num_samples} n={n} cf={f.use_cf} near={near} "
+         f"linear={linear} acc={acc} L={L} dec={dec}")
+    kw = dict(linear=linear, accumulate=acc)
+    y = _run(f, f.x_f32(), **kw)
+    env = _run(f, f.x_f32(), env=True, taps=taps, env_decimation=dec, **kw)
+    y_ref = oracle.frame_rows(f, x=f.x_f32().astype(np.float64), interp=linear)
+    env_ref = oracle.envelope(y_ref, taps.astype(np.float64))[:, ::dec]
+    assert env.shape == env_ref.shape
+    check_t1(y, y_ref)
+    check_t1(env, env_ref)
+
+
 def test_bad_output_buffers_rejected():
     """Output tensors of the wrong shape, type, layout or device are refused before any launch."""
     f = synth.random_frame(np.random.default_rng(97), 8, 5, 100, 2)
