@@ -197,7 +197,8 @@ dmas_status_t dmas_matched_filter(dmas_plan_t plan, const float *d_raw, float *d
 /* The steering delays the beamformer uses, eq. (1), computed by the same
  * device code: d_whole (D x M int32, device) receives floor(fs*tau + 1/2) in
  * NEAREST mode and floor(fs*tau) in LINEAR mode; d_frac (D x M FP32, device,
- * may be NULL) receives fs*tau - floor(fs*tau) in LINEAR mode and 0 otherwise. */
+ * may be NULL) receives fs*tau - floor(fs*tau) in LINEAR mode and 0 otherwise.
+ * The plan's device must be current (DMAS_ERR_INVALID_ARG otherwise). */
 dmas_status_t dmas_steering_delays(dmas_plan_t plan, int32_t *d_whole, float *d_frac,
                                    void *stream);
 
@@ -248,8 +249,9 @@ typedef struct {
     double t_admit;        /* device memory granted, input copy issued */
     double t_launch;       /* launch issued */
     double t_done;         /* completion observed */
-    float *d_out;          /* device result, D x T FP32; NULL once released */
-    int64_t pixels;        /* D * T */
+    float *d_out;          /* device result, D x T FP32 (D x ceil(T/k) for an envelope with
+                              env_decimation k); NULL until done and once released */
+    int64_t pixels;        /* D * T, the beamformed pixels (before any decimation) */
 } dmas_frame_info_t;
 
 typedef struct {
@@ -277,7 +279,8 @@ dmas_status_t dmas_server_submit(dmas_server_t srv, dmas_plan_t plan, const void
 dmas_status_t dmas_server_query(dmas_server_t srv, uint64_t ticket, dmas_frame_info_t *info);
 
 /* Block until the frame is done or failed, or timeout seconds pass
- * (DMAS_ERR_TIMEOUT). */
+ * (DMAS_ERR_TIMEOUT). timeout >= 0 (NaN or negative: DMAS_ERR_INVALID_ARG);
+ * values above 1e9, infinity included, wait 1e9 seconds. */
 dmas_status_t dmas_server_wait(dmas_server_t srv, uint64_t ticket, double timeout, dmas_frame_info_t *info);
 
 /* Return a done frame's device memory to the arena and forget the ticket. */
@@ -292,7 +295,8 @@ dmas_status_t dmas_server_fetch(dmas_server_t srv, uint64_t ticket, float *h_out
  * (oldest first); *count receives how many. */
 dmas_status_t dmas_server_completed(dmas_server_t srv, dmas_frame_info_t *out, int32_t max, int32_t *count);
 
-/* Block until nothing is queued, admitted or in flight (or timeout). */
+/* Block until nothing is queued, admitted or in flight (or timeout, taken as
+ * in dmas_server_wait). */
 dmas_status_t dmas_server_drain(dmas_server_t srv, double timeout);
 
 dmas_status_t dmas_server_stats(dmas_server_t srv, dmas_server_stats_t *stats);

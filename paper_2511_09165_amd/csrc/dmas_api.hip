@@ -828,6 +828,9 @@ dmas_status_t dmas_matched_filter(dmas_plan_t p, const float *d_raw, float *d_x,
 dmas_status_t dmas_steering_delays(dmas_plan_t p, int32_t *d_whole, float *d_frac, void *stream)
 {
     if (!p || !d_whole) return fail(DMAS_ERR_INVALID_ARG, "plan or d_whole is NULL");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(DMAS_ERR_INVALID_ARG, "plan belongs to device %d but device %d is current", p->device, cur);
     const int64_t n = (int64_t)p->M * p->D;
     const int threads = 256;
     const int64_t blocks = (n + threads - 1) / threads;

@@ -40,6 +40,16 @@ double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Deadline `timeout` seconds from now on the steady clock. Waits are capped at
+// kMaxWait seconds (infinity included) so the deadline stays representable.
+constexpr double kMaxWait = 1.0e9;
+std::chrono::steady_clock::time_point deadline_after(double timeout)
+{
+    using namespace std::chrono;
+    const double t = std::min(timeout, kMaxWait);
+    return steady_clock::now() + duration_cast<steady_clock::duration>(duration<double>(t));
+}
+
 // First-fit allocator over [0, size) with coalescing of free ranges.
 class Arena {
 public:
@@ -236,6 +246,27 @@ struct dmas_server_s {
         f->staged = false;
     }
 
+    // A frame that failed before its launch completed (input copy or launch
+    // call): memory and event returned, and an auto-released frame reported
+    // through the completed records, as a frame whose launch failed on the
+    // device is. The caller has made the frame's streams idle.
+    void fail_unlaunched(Frame *f)
+    {
+        f->state = kFailed;
+        f->t_done = now_s();
+        ++n_failed;
+        free_staging(f);
+        free_device(f);
+        if (f->copied) event_pool.push_back(f->copied), f->copied = nullptr;
+        if (f->auto_release) {
+            dmas_frame_info_t info;
+            fill_info(f, &info);
+            finished.push_back(info);
+            frames.erase(f->ticket);
+            delete f;
+        }
+    }
+
     // ---- scheduler steps (called with mu held) ----
     bool collect_completions()
     {
@@ -308,10 +339,8 @@ struct dmas_server_s {
             f->t_admit = now_s();
             queued.pop_front();
             if (e != hipSuccess || !f->copied) {
-                f->state = kFailed;
-                ++n_failed;
-                free_device(f);
-                free_staging(f);
+                (void)hipStreamSynchronize(copy_stream);   // done with the staging and arena ranges
+                fail_unlaunched(f);
                 worker_error = "input copy failed";
                 cv_done.notify_all();
             } else {
@@ -444,15 +473,8 @@ struct dmas_server_s {
             if (e != hipSuccess) {
                 // The launch did not happen: fail its frames now (their event may never fire).
                 worker_error = hipGetErrorString(e);
-                hipError_t sync = hipStreamSynchronize(st);
-                (void)sync;
-                for (Frame *f : group) {
-                    f->state = kFailed;
-                    f->t_done = now_s();
-                    ++n_failed;
-                    free_staging(f);
-                    free_device(f);
-                }
+                (void)hipStreamSynchronize(st);
+                for (Frame *f : group) fail_unlaunched(f);
                 l.frames.clear();
                 l.busy = false;
                 cv_done.notify_all();
@@ -632,8 +654,9 @@ dmas_status_t dmas_server_query(dmas_server_t s, uint64_t ticket, dmas_frame_inf
 dmas_status_t dmas_server_wait(dmas_server_t s, uint64_t ticket, double timeout, dmas_frame_info_t *info)
 {
     if (!s) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL server");
+    if (!(timeout >= 0.0)) return srv_fail(DMAS_ERR_INVALID_ARG, "timeout must be >= 0");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout);
+    const auto deadline = deadline_after(timeout);
     while (true) {
         auto it = s->frames.find(ticket);
         if (it == s->frames.end()) return srv_fail(DMAS_ERR_INVALID_ARG, "unknown ticket");
@@ -702,8 +725,9 @@ dmas_status_t dmas_server_completed(dmas_server_t s, dmas_frame_info_t *out, int
 dmas_status_t dmas_server_drain(dmas_server_t s, double timeout)
 {
     if (!s) return srv_fail(DMAS_ERR_INVALID_ARG, "NULL server");
+    if (!(timeout >= 0.0)) return srv_fail(DMAS_ERR_INVALID_ARG, "timeout must be >= 0");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout);
+    const auto deadline = deadline_after(timeout);
     while (true) {
         bool busy = !s->queued.empty() || !s->admitted.empty();
         for (auto &l : s->launches) busy |= l.busy;

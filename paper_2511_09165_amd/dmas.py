@@ -334,12 +334,16 @@ class Server:
         d = ServerDesc(int(hbm_budget), int(staging), int(num_streams), int(max_batch))
         self._h = ctypes.c_void_p()
         self._shapes = {}   # ticket -> result shape, for frames whose result stays on the device
+        # the library keeps a pointer to each frame's plan: hold the Plan objects until the
+        # server is closed, so that a frame in flight never outlives its plan by garbage collection
+        self._plans = {}
         _check(self._lib.dmas_server_create(ctypes.byref(d), ctypes.byref(self._h)))
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.dmas_server_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._plans = {}
 
     def __del__(self):
         try:
@@ -362,6 +366,7 @@ class Server:
             raise ValueError(f"x must be a contiguous {np.dtype(want)} array of shape "
                              f"({plan.num_mics}, {plan.num_samples})")
         flags = (SUBMIT_ENVELOPE if envelope else 0) | (SUBMIT_AUTO_RELEASE if auto_release else 0)
+        self._plans[id(plan)] = plan
         t = ctypes.c_uint64()
         _check(self._lib.dmas_server_submit(self._h, ctypes.c_void_p(plan.handle),
                                             xa.ctypes.data_as(ctypes.c_void_p), float(in_scale), flags,

@@ -193,7 +193,14 @@ def test_rejections_and_release_rules():
             srv.release(t2)
         except DmasError as err:
             assert err.status == 5                    # DMAS_ERR_BUSY
-        srv.wait(t1)
+        srv.wait(t1, timeout=float("inf"))           # no limit: capped, not overflowed
+        for bad in (float("nan"), -1.0):
+            with pytest.raises(DmasError) as e:
+                srv.wait(t1, timeout=bad)
+            assert e.value.status == 1
+            with pytest.raises(DmasError):
+                srv.drain(bad)
+        srv.drain(float("inf"))
         with pytest.raises(ValueError):
             srv.fetch(t1, (100, 4095))                # not the result's shape (binding check)
         assert srv.fetch(t1).shape == (100, 4096)     # the envelope's (D, T)
@@ -224,3 +231,20 @@ def test_auto_release_records():
         assert r["t_arrival"] <= r["t_admit"] <= r["t_launch"] <= r["t_done"]
     for p in plans:
         p.close()
+
+
+def test_server_holds_its_plans():
+    """A frame submitted with a Plan that the caller no longer references still runs on a live
+    plan (the binding holds it until the server closes) and gives the plain launch's bits."""
+    import gc
+    from paper_2511_09165_amd import Server, plan_for_frame
+    f = synth.random_frame(np.random.default_rng(17), 16, 40, 2048, 3)
+    _say("server holds plans")
+    with plan_for_frame(f) as p:
+        ref = _standalone(p, f.x_f32(), True)
+    with Server(hbm_budget=1 << 28) as srv:
+        t = srv.submit(plan_for_frame(f), f.x_f32())
+        gc.collect()
+        srv.wait(t)
+        np.testing.assert_array_equal(srv.fetch(t), ref)
+        srv.release(t)
