@@ -222,6 +222,18 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  *     nearest delays, plain sums; others are launched one by one) on the next
  *     free compute stream, so a new batch starts while earlier ones finish;
  *   - completion is observed from stream events and stamped per frame.
+ * With `resident` set, frames of orders 3 and 5 whose plan reads its delays
+ * from tables (nearest delays, plain sums) are served instead by a resident
+ * worker: one persistent launch per kernel class whose workgroups take work
+ * items (a frame's root-plane chunks, then its (tile, segment) workgroups) from
+ * a queue of job descriptors that the scheduler writes into pinned host memory
+ * while the launch runs, so frames start without a launch each. A worker serves
+ * one class and plans created before its launch; a frame of another class or
+ * a newer plan lets the worker finish its queue and exit, and the next worker is
+ * launched for it. Workers exit after about 7 ms without work, and when the
+ * server is destroyed. While a worker runs it holds the compute units it was
+ * launched on, so other kernels on the device (other frames' launches, plan
+ * creation) start when it exits.
  * Each frame's pixels are computed by the same device code as
  * dmas_beamform / dmas_envelope, so a frame gives the same bits alone and
  * in a batch. Plans stay owned by the caller and must outlive their frames.
@@ -234,6 +246,8 @@ typedef struct {
     int64_t staging_bytes;     /* pinned host memory for queued inputs; 0 selects 256 MiB */
     int32_t num_streams;       /* launches in flight at once; 0 selects 2 */
     int32_t max_batch_frames;  /* frames per launch; 0 selects 64; 1 = one plain launch per frame */
+    int32_t resident;          /* 1: serve the frames that have a resident worker through one (below); 0: launches only */
+    int32_t reserved;          /* 0 */
 } dmas_server_desc_t;
 
 /* submit flags */
@@ -258,6 +272,8 @@ typedef struct {
     int64_t submitted, completed, failed, launches, batched_frames;
     int64_t queued, admitted_not_launched, in_flight;
     int64_t hbm_in_use, hbm_peak, hbm_budget;
+    int64_t resident_launches;  /* resident worker launches */
+    int64_t resident_frames;    /* frames served by resident workers */
 } dmas_server_stats_t;
 
 /* Seconds on the serving clock (monotonic). */

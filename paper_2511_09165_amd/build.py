@@ -18,7 +18,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdmas.so")
 ARCH = os.environ.get("DMAS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["dmas_api.hip", "dmas_batch.hip", "dmas_server.hip", "dmas_mf.hip", "dmas_roots.hip"] + [f"dmas_order{n}.hip" for n in range(1, 9)]
+SOURCES = (["dmas_api.hip", "dmas_batch.hip", "dmas_server.hip", "dmas_mf.hip", "dmas_roots.hip"]
+           + [f"dmas_order{n}.hip" for n in range(1, 9)] + ["dmas_resident3.hip", "dmas_resident5.hip"])
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

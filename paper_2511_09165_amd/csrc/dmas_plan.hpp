@@ -4,12 +4,23 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 
 #include "dmas_internal.hpp"
 
+namespace dmas {
+// Source of plan serial numbers, in creation order.
+inline std::atomic<uint64_t> &plan_serials()
+{
+    static std::atomic<uint64_t> next{1};
+    return next;
+}
+}  // namespace dmas
+
 struct dmas_plan_s {
+    uint64_t serial = dmas::plan_serials().fetch_add(1);   // creation order
     int device = 0;
     int M = 0, T = 0, D = 0, order = 0;
     bool cf = true, nearfield = false, linear = false;

@@ -1,0 +1,174 @@
+// Resident worker kernel (device code), one instantiation per kernel class;
+// included by the per-order units dmas_resident<n>.hip. Queue layout and
+// memory ordering are described in dmas_resident.hpp.
+#pragma once
+
+#include <cstring>
+
+#include "dmas_kernel.hpp"
+#include "dmas_resident.hpp"
+
+namespace dmas {
+
+constexpr int32_t kClaimIdle = -1;   // nothing to claim now
+constexpr int32_t kClaimExit = -2;   // nothing to claim and the host asked the workers to stop
+constexpr int kClaimTries = 64;      // jobs passed over per claim before reporting idle
+
+__device__ __forceinline__ int32_t load_acquire_sys(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Thread 0 of a workgroup: the next (job, item), or (kClaimIdle | kClaimExit, 0).
+// pub_seen caches the last published count this workgroup read; jobs below it
+// are complete in host memory. Items are handed out in job order: a job's
+// counter is raised until it passes the job's item count, then cur_job moves on.
+__device__ __forceinline__ int2 claim_item(const ResidentArgs &a, int &pub_seen)
+{
+    ResidentDevice *dv = a.dev;
+    int j = __hip_atomic_load(&dv->cur_job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int tries = 0; tries < kClaimTries; ++tries) {
+        if (j >= pub_seen) {
+            // stop first: a stop seen here means every job was published before it
+            const int stop = load_acquire_sys(&a.host->stop);
+            pub_seen = load_acquire_sys(&a.host->published);
+            if (j >= pub_seen) return make_int2(stop ? kClaimExit : kClaimIdle, 0);
+        }
+        const int items = __hip_atomic_load(&a.host->jobs[j].items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const int i = __hip_atomic_fetch_add(&dv->claimed[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (i < items) return make_int2(j, i);
+        int expected = j;
+        __hip_atomic_compare_exchange_strong(&dv->cur_job, &expected, j + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        j = expected == j ? j + 1 : expected;   // cur_job only grows: expected > j on failure
+    }
+    return make_int2(kClaimIdle, 0);
+}
+
+template <int N>
+__device__ __forceinline__ void roots_item(const ResidentJob &jd, int item)
+{
+    float2 *plane = const_cast<float2 *>(jd.kp.roots);
+    const int64_t e0 = (int64_t)item * kRootItem;
+    const int64_t e1 = e0 + kRootItem < jd.count ? e0 + kRootItem : jd.count;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const float v = jd.kp.dtype == 0   ? load_sample<0>(jd.kp.x, (size_t)e)
+                        : jd.kp.dtype == 1 ? load_sample<1>(jd.kp.x, (size_t)e)
+                                           : load_sample<2>(jd.kp.x, (size_t)e);
+        plane[e] = make_float2(signed_root<N>(v), v);
+    }
+}
+
+template <int N, bool CF, bool ENV, bool NEAR, int DM>
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, kAccF32, DM>))
+dmas_resident_kernel(const ResidentArgs a)
+{
+    extern __shared__ float smem[];
+    __shared__ int32_t s_cmd[2];
+    __shared__ uint32_t s_job[kJobWords];
+    const int tid = threadIdx.x;
+    int pub_seen = 0;       // thread 0 only
+    int have = -1;          // job whose descriptor is in s_job (the same in every thread)
+    int dep_ready = -1;     // roots job known complete by this workgroup
+    int idle = 0;
+    for (;;) {
+        if (tid == 0) {
+            const int2 c = claim_item(a, pub_seen);
+            s_cmd[0] = c.x;
+            s_cmd[1] = c.y;
+        }
+        __syncthreads();
+        const int job = __builtin_amdgcn_readfirstlane(s_cmd[0]);
+        const int item = __builtin_amdgcn_readfirstlane(s_cmd[1]);
+        __syncthreads();   // every thread has read s_cmd before thread 0 writes it again
+        if (job == kClaimExit) break;
+        if (job == kClaimIdle) {
+            if (++idle > a.idle_limit) break;
+            __builtin_amdgcn_s_sleep(127);
+            continue;
+        }
+        idle = 0;
+        if (job != have) {
+            // first item of this job here: see its inputs (copied by the host or
+            // written by other workgroups) and read its descriptor
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            const int32_t *src = reinterpret_cast<const int32_t *>(&a.host->jobs[job]);
+            for (int w = tid; w < kJobWords; w += blockDim.x)
+                s_job[w] = (uint32_t)__hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __syncthreads();
+            have = job;
+        }
+        uint32_t words[kJobWords];
+#pragma unroll
+        for (int w = 0; w < kJobWords; ++w) words[w] = __builtin_amdgcn_readfirstlane(s_job[w]);
+        ResidentJob jd;
+        __builtin_memcpy(&jd, words, sizeof jd);
+        if (jd.kind == kJobRoots) {
+            roots_item<N>(jd, item);
+        } else {
+            if (jd.dep >= 0 && jd.dep != dep_ready) {
+                if (tid == 0) {
+                    int k = 0;
+                    while (__hip_atomic_load(&a.dev->finished[jd.dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           jd.dep_items) {
+                        if (++k > a.dep_limit) {
+                            __hip_atomic_store(&a.host->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // the plane written by other workgroups
+                dep_ready = jd.dep;
+            }
+            dmas_body<N, CF, ENV, NEAR, DM, kAccF32>(jd.kp, item % jd.kp.num_tiles, item / jd.kp.num_tiles, smem);
+        }
+        // this item's stores reach memory before it is counted
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __syncthreads();
+        if (tid == 0) {
+            const int prev =
+                __hip_atomic_fetch_add(&a.dev->finished[job], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev + 1 == jd.items)
+                __hip_atomic_store(&a.host->done[job], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
+template <int N, bool CF, bool ENV, bool NEAR, int DM>
+hipError_t resident_one(const ResidentArgs &a, unsigned grid, size_t lds, hipStream_t stream, int *blocks)
+{
+    auto fn = dmas_resident_kernel<N, CF, ENV, NEAR, DM>;
+    if (blocks)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(fn),
+                                                            kDirsPerTile * kWaveSize, lds);
+    static std::atomic<size_t> allowed{64 * 1024};
+    hipError_t e = raise_lds_limit(reinterpret_cast<const void *>(fn), lds, allowed);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kDirsPerTile * kWaveSize), lds, stream, a);
+    return hipGetLastError();
+}
+
+// Classes with a worker: CF or not, envelope or not, either geometry; delays
+// from the per-tile tables (either table mode).
+template <int N>
+hipError_t launch_resident_order(bool cf, bool env, bool nearfield, int delay, const ResidentArgs &a, unsigned grid,
+                                 size_t lds, hipStream_t stream, int *blocks)
+{
+#define DMAS_RES(CF, ENV, NEAR, DM)                                                   \
+    if (cf == CF && env == ENV && nearfield == NEAR && delay == DM)                   \
+        return resident_one<N, CF, ENV, NEAR, DM>(a, grid, lds, stream, blocks);
+#define DMAS_RES_DM(DM)                                                                \
+    DMAS_RES(true, true, false, DM) DMAS_RES(true, false, false, DM)                  \
+    DMAS_RES(true, true, true, DM) DMAS_RES(true, false, true, DM)                    \
+    DMAS_RES(false, true, false, DM) DMAS_RES(false, false, false, DM)                \
+    DMAS_RES(false, true, true, DM) DMAS_RES(false, false, true, DM)
+    DMAS_RES_DM(kDelayTable)
+    DMAS_RES_DM(kDelayTableLanes)
+#undef DMAS_RES_DM
+#undef DMAS_RES
+    return hipErrorNotSupported;
+}
+
+}  // namespace dmas

@@ -23,6 +23,7 @@
 #include "../../include/dmas.h"
 #include "dmas_internal.hpp"
 #include "dmas_plan.hpp"
+#include "dmas_resident.hpp"
 
 namespace {
 
@@ -115,6 +116,7 @@ struct Frame {
     size_t in_off = 0, out_off = 0;
     size_t plane_bytes = 0, plane_off = 0;   // root plane (plans that stage roots)
     bool on_device = false;
+    bool resident = false;   // served by a resident worker
     hipEvent_t copied = nullptr;
     int state = kQueued;
     int batch_frames = 0;
@@ -166,7 +168,35 @@ dmas_status_t srv_fail(dmas_status_t st, const char *msg)
     return st;
 }
 
+// Resident workers: polls (about 3.4 us each at 2.4 GHz) before an idle
+// workgroup exits; polls (about 0.2 us each) of a root plane before a
+// workgroup gives up on it; how long a worker takes new jobs; how long a frame
+// of another class waits before the worker is asked to exit.
+constexpr int32_t kResidentIdlePolls = 2000;
+constexpr int32_t kResidentDepPolls = 1 << 22;
+constexpr double kResidentLife = 0.020;
+constexpr double kResidentSwitchWait = 0.001;
+
+// Frames that a resident worker serves: nearest delays from the per-tile
+// tables, plain sums, orders 3 and 5.
+bool resident_capable(const dmas_plan_s *p, bool env)
+{
+    if (!batchable(p) || (p->order != 3 && p->order != 5)) return false;
+    const int dm = dmas::shape_of(p, env).delay;
+    return dm == dmas::kDelayTable || dm == dmas::kDelayTableLanes;
+}
+
 }  // namespace
+
+hipError_t dmas::launch_resident(int order, bool cf, bool env, bool nearfield, int delay, const ResidentArgs &a,
+                                 unsigned grid, size_t lds, hipStream_t stream, int *blocks)
+{
+    switch (order) {
+    case 3: return launch_resident_order3(cf, env, nearfield, delay, a, grid, lds, stream, blocks);
+    case 5: return launch_resident_order5(cf, env, nearfield, delay, a, grid, lds, stream, blocks);
+    default: return hipErrorNotSupported;
+    }
+}
 
 struct dmas_server_s {
     int device = 0;
@@ -192,6 +222,25 @@ struct dmas_server_s {
     std::deque<dmas_frame_info_t> finished;   // records of auto-released frames
     uint64_t next_ticket = 1;
     int64_t n_submitted = 0, n_completed = 0, n_failed = 0, n_launches = 0, n_batched = 0;
+
+    // ---- resident workers (one at a time, one kernel class each) ----
+    bool res_on = false;
+    dmas::ResidentHost *res_h = nullptr;    // pinned job queue, host view
+    dmas::ResidentHost *res_hd = nullptr;   // the same memory, device view
+    dmas::ResidentDevice *res_d = nullptr;
+    hipStream_t res_stream = nullptr;
+    hipEvent_t res_end = nullptr;
+    bool res_running = false, res_stopping = false;
+    int res_order = 0, res_delay = 0;
+    bool res_cf = false, res_env = false, res_near = false;
+    size_t res_lds = 0;
+    uint64_t res_serial = 0;                // the worker serves plans with smaller serials
+    double res_t_launch = 0;
+    int res_published = 0, res_checked = 0; // jobs written / jobs seen done
+    std::vector<Frame *> res_job_frame;     // per job: its frame for a pixels job, else null
+    std::deque<Frame *> res_admitted;       // admitted frames for the resident workers
+    int res_cus = 256;
+    int64_t n_res_launches = 0, n_res_frames = 0;
 
     std::mutex mu;
     std::condition_variable cv_done;     // frame completions, for waiters
@@ -331,10 +380,12 @@ struct dmas_server_s {
             f->on_device = true;
             hbm_peak = std::max(hbm_peak, arena.used());
             f->copied = get_event();
-            // input copy, then the root plane, both on the copy stream
+            f->resident = res_on && resident_capable(f->plan, f->env);
+            // input copy, then the root plane (resident frames: the worker's), on the copy stream
             hipError_t e = hipMemcpyAsync(d_arena + in_off, h_staging + f->stage_off, f->in_bytes,
                                           hipMemcpyHostToDevice, copy_stream);
-            if (e == hipSuccess && f->plane_bytes) e = dmas::stage_roots(f->plan, d_arena + in_off, plane_of(f), copy_stream);
+            if (e == hipSuccess && f->plane_bytes && !f->resident)
+                e = dmas::stage_roots(f->plan, d_arena + in_off, plane_of(f), copy_stream);
             if (e == hipSuccess && f->copied) e = hipEventRecord(f->copied, copy_stream);
             f->t_admit = now_s();
             queued.pop_front();
@@ -345,7 +396,7 @@ struct dmas_server_s {
                 cv_done.notify_all();
             } else {
                 f->state = kAdmitted;
-                admitted.push_back(f);
+                (f->resident ? res_admitted : admitted).push_back(f);
             }
             progress = true;
         }
@@ -484,6 +535,213 @@ struct dmas_server_s {
         return progress;
     }
 
+    // ---- resident workers (called with mu held) ----
+    // A frame whose pixels job is done.
+    void res_finish(Frame *f)
+    {
+        const bool ok = __atomic_load_n(&res_h->error, __ATOMIC_ACQUIRE) == 0;
+        f->t_done = now_s();
+        f->state = ok ? kDone : kFailed;
+        free_staging(f);
+        if (f->copied) event_pool.push_back(f->copied), f->copied = nullptr;
+        if (ok) ++n_completed; else ++n_failed;
+        if (!ok) worker_error = "a resident worker gave up waiting for a root plane";
+        if (f->auto_release || !ok) {
+            free_device(f);
+            if (f->auto_release) {
+                dmas_frame_info_t info;
+                fill_info(f, &info);
+                finished.push_back(info);
+                frames.erase(f->ticket);
+                delete f;
+            }
+        }
+    }
+
+    // Fail the frames of every job not seen done and empty the queue (after a
+    // worker launch failed or a worker ended with an error; the worker stream is idle).
+    void res_fail_outstanding(const char *why)
+    {
+        worker_error = why;
+        for (int j = res_checked; j < res_published; ++j)
+            if (Frame *f = res_job_frame[j]) fail_unlaunched(f);
+        res_checked = res_published;
+    }
+
+    // Launch a worker for the current class; reset starts a new queue
+    // generation (every published job done), else the worker continues the
+    // queue as it stands.
+    bool res_launch(bool reset)
+    {
+        hipError_t e = hipSuccess;
+        if (reset) {
+            e = hipMemsetAsync(res_d, 0, sizeof(dmas::ResidentDevice), res_stream);
+            std::memset(res_h->done, 0, sizeof(int32_t) * (size_t)res_published);
+            __atomic_store_n(&res_h->error, 0, __ATOMIC_RELAXED);
+            __atomic_store_n(&res_h->published, 0, __ATOMIC_RELEASE);
+            res_published = res_checked = 0;
+            res_job_frame.clear();
+        }
+        __atomic_store_n(&res_h->stop, 0, __ATOMIC_RELEASE);
+        res_serial = dmas::plan_serials().load();
+        const dmas::ResidentArgs a{res_hd, res_d, kResidentIdlePolls, kResidentDepPolls};
+        int blocks = 0;
+        if (e == hipSuccess)
+            e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, 0, res_lds, res_stream, &blocks);
+        if (e == hipSuccess && blocks < 1) e = hipErrorInvalidConfiguration;
+        if (e == hipSuccess)
+            e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, (unsigned)(blocks * res_cus),
+                                      res_lds, res_stream, nullptr);
+        if (e == hipSuccess) e = hipEventRecord(res_end, res_stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(res_stream);
+            res_fail_outstanding(hipGetErrorString(e));
+            return false;
+        }
+        res_running = true;
+        res_stopping = false;
+        res_t_launch = now_s();
+        ++n_res_launches;
+        return true;
+    }
+
+    // Write a frame's jobs (roots, then pixels) and publish them.
+    void res_publish(Frame *f)
+    {
+        const dmas::KernelParams kp = dmas::make_params(
+            f->plan, d_arena + f->in_off, plane_of(f), reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale,
+            f->env);
+        int dep = -1, dep_items = 0;
+        if (f->plane_bytes) {
+            dmas::ResidentJob &r = res_h->jobs[res_published];
+            r.kp = kp;
+            r.kind = dmas::kJobRoots;
+            r.count = (int64_t)f->plan->M * f->plan->T;
+            r.items = (int32_t)((r.count + dmas::kRootItem - 1) / dmas::kRootItem);
+            r.dep = -1;
+            r.dep_items = 0;
+            dep = res_published;
+            dep_items = r.items;
+            res_job_frame.push_back(nullptr);
+            ++res_published;
+        }
+        dmas::ResidentJob &j = res_h->jobs[res_published];
+        j.kp = kp;
+        j.kind = dmas::kJobPixels;
+        j.count = 0;
+        j.items = (int32_t)dmas::plan_workgroups(f->plan, f->env);
+        j.dep = dep;
+        j.dep_items = dep_items;
+        res_job_frame.push_back(f);
+        ++res_published;
+        __atomic_store_n(&res_h->published, res_published, __ATOMIC_RELEASE);
+        f->state = kLaunched;
+        f->t_launch = now_s();
+        f->batch_frames = 1;
+        ++n_res_frames;
+    }
+
+    bool res_same_class(const Frame *f) const
+    {
+        return f->plan->order == res_order && f->plan->cf == res_cf && f->env == res_env &&
+               f->plan->nearfield == res_near && dmas::shape_of(f->plan, f->env).delay == res_delay;
+    }
+
+    bool resident_step()
+    {
+        if (!res_on) return false;
+        bool progress = false;
+        // jobs done, in queue order
+        while (res_checked < res_published && __atomic_load_n(&res_h->done[res_checked], __ATOMIC_ACQUIRE)) {
+            if (Frame *f = res_job_frame[res_checked]) res_finish(f);
+            ++res_checked;
+            progress = true;
+        }
+        if (res_running) {
+            const hipError_t q = hipEventQuery(res_end);
+            if (q != hipErrorNotReady) {
+                res_running = false;
+                res_stopping = false;
+                progress = true;
+                if (q != hipSuccess) res_fail_outstanding(hipGetErrorString(q));
+                // a worker that ended has completed every job it claimed: read the flags again
+                while (res_checked < res_published && __atomic_load_n(&res_h->done[res_checked], __ATOMIC_ACQUIRE)) {
+                    if (Frame *f = res_job_frame[res_checked]) res_finish(f);
+                    ++res_checked;
+                }
+            }
+        }
+        // jobs published after the last workgroup went idle: continue the queue
+        if (!res_running && res_checked < res_published) {
+            res_launch(false);
+            return true;
+        }
+        const double t_now = now_s();
+        const bool can_take = res_running && !res_stopping && t_now - res_t_launch < kResidentLife;
+        double oldest_other = -1;   // admission time of the oldest frame the worker cannot take
+        for (auto it = res_admitted.begin(); it != res_admitted.end();) {
+            Frame *f = *it;
+            const hipError_t q = hipEventQuery(f->copied);
+            if (q == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            if (q != hipSuccess) {
+                it = res_admitted.erase(it);
+                fail_unlaunched(f);
+                worker_error = "input copy failed";
+                progress = true;
+                continue;
+            }
+            if (!res_running && !res_stopping && res_checked == res_published) {
+                // no worker: launch one for this frame's class with the largest LDS that the
+                // class's admitted frames need
+                res_order = f->plan->order;
+                res_cf = f->plan->cf;
+                res_env = f->env;
+                res_near = f->plan->nearfield;
+                res_delay = dmas::shape_of(f->plan, f->env).delay;
+                res_lds = 0;
+                for (Frame *g : res_admitted)
+                    if (res_same_class(g)) res_lds = std::max(res_lds, g->env ? g->plan->lds_env : g->plan->lds_rf);
+                if (!res_launch(true)) {
+                    it = res_admitted.erase(it);
+                    fail_unlaunched(f);
+                    progress = true;
+                    continue;
+                }
+                progress = true;
+            }
+            const size_t lds = f->env ? f->plan->lds_env : f->plan->lds_rf;
+            const bool fits = (can_take || (res_running && !res_stopping && t_now - res_t_launch < kResidentLife)) &&
+                              res_same_class(f) && lds <= res_lds && f->plan->serial < res_serial &&
+                              res_published + 2 <= dmas::kResidentJobs;
+            if (fits) {
+                it = res_admitted.erase(it);
+                res_publish(f);
+                progress = true;
+            } else {
+                if (oldest_other < 0) oldest_other = f->t_admit;
+                ++it;
+            }
+        }
+        // let the worker finish its queue and exit when a frame it cannot take has waited,
+        // when it has nothing left, when it has run its time, or when launches wait for the device
+        if (res_running && !res_stopping) {
+            const bool idle = res_checked == res_published;
+            bool launches_wait = !admitted.empty();
+            for (auto &l : launches) launches_wait |= l.busy;
+            if ((oldest_other >= 0 && (idle || t_now - oldest_other > kResidentSwitchWait)) ||
+                t_now - res_t_launch >= kResidentLife || launches_wait || res_published + 2 > dmas::kResidentJobs) {
+                __atomic_store_n(&res_h->stop, 1, __ATOMIC_RELEASE);
+                res_stopping = true;
+                progress = true;
+            }
+        }
+        if (progress) cv_done.notify_all();
+        return progress;
+    }
+
     void run()
     {
         std::unique_lock<std::mutex> lk(mu);
@@ -493,11 +751,12 @@ struct dmas_server_s {
         while (!stop.load()) {
             bool progress = collect_completions();
             progress |= admit();
+            progress |= resident_step();
             progress |= launch();
-            bool busy = false;
+            bool busy = res_running;
             for (auto &l : launches) busy |= l.busy;
             if (!progress) {
-                if (!busy && queued.empty() && admitted.empty()) {
+                if (!busy && queued.empty() && admitted.empty() && res_admitted.empty()) {
                     cv_work.wait_for(lk, std::chrono::milliseconds(5));
                 } else {
                     lk.unlock();
@@ -525,6 +784,8 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
         return srv_fail(DMAS_ERR_INVALID_ARG, "negative server parameter");
     if (d->max_batch_frames > kMaxBatchFrames) return srv_fail(DMAS_ERR_INVALID_ARG, "max_batch_frames > 1024");
     if (d->num_streams > 16) return srv_fail(DMAS_ERR_INVALID_ARG, "num_streams > 16");
+    if ((d->resident != 0 && d->resident != 1) || d->reserved != 0)
+        return srv_fail(DMAS_ERR_INVALID_ARG, "resident must be 0 or 1 and reserved 0");
     auto *s = new (std::nothrow) dmas_server_s();
     if (!s) return srv_fail(DMAS_ERR_OUT_OF_MEMORY, "host allocation failed");
     if (hipGetDevice(&s->device) != hipSuccess) {
@@ -543,6 +804,7 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
             cus = prop.multiProcessorCount;
             if (prop.clockRate > 0) clk = prop.clockRate * 1e3;
         }
+        s->res_cus = cus;
         s->resident_wgs = (int64_t)3 * cus;
         // 4 SIMDs x 16 lanes per CU issue one lane-instruction each per clock
         s->rate_cap = 0.92 * cus * 64.0 * clk;
@@ -584,6 +846,27 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
     }
     if ((e = hipMemcpyAsync(s->d_tables[0], s->h_tables[0], kAlign, hipMemcpyHostToDevice, s->copy_stream)) != hipSuccess)
         return fail_all(e, "copy stream warm-up");
+    if (d->resident) {
+        // the job queue in coherent pinned memory (polled by the device), the claim
+        // counters on the device
+        s->res_on = true;
+        if ((e = hipHostMalloc((void **)&s->res_h, sizeof(dmas::ResidentHost), hipHostMallocCoherent | hipHostMallocMapped)) !=
+            hipSuccess)
+            return fail_all(e, "resident job queue");
+        std::memset(s->res_h, 0, sizeof(dmas::ResidentHost));
+        if ((e = hipHostGetDevicePointer((void **)&s->res_hd, s->res_h, 0)) != hipSuccess)
+            return fail_all(e, "resident job queue (device view)");
+        if ((e = hipMalloc((void **)&s->res_d, sizeof(dmas::ResidentDevice))) != hipSuccess)
+            return fail_all(e, "resident counters");
+        if ((e = hipStreamCreateWithFlags(&s->res_stream, hipStreamNonBlocking)) != hipSuccess)
+            return fail_all(e, "resident stream");
+        if ((e = hipEventCreateWithFlags(&s->res_end, hipEventDisableTiming)) != hipSuccess)
+            return fail_all(e, "resident event");
+        if ((e = hipMemsetAsync(s->res_d, 0, sizeof(dmas::ResidentDevice), s->res_stream)) != hipSuccess ||
+            (e = hipEventRecord(s->res_end, s->res_stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(s->res_stream)) != hipSuccess)
+            return fail_all(e, "resident stream warm-up");
+    }
     for (hipStream_t st : s->streams)
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_all(e, "stream warm-up");
     if ((e = hipStreamSynchronize(s->copy_stream)) != hipSuccess) return fail_all(e, "copy stream warm-up");
@@ -728,13 +1011,17 @@ dmas_status_t dmas_server_drain(dmas_server_t s, double timeout)
     if (!(timeout >= 0.0)) return srv_fail(DMAS_ERR_INVALID_ARG, "timeout must be >= 0");
     std::unique_lock<std::mutex> lk(s->mu);
     const auto deadline = deadline_after(timeout);
-    while (true) {
-        bool busy = !s->queued.empty() || !s->admitted.empty();
+    auto busy_now = [s] {
+        bool busy = !s->queued.empty() || !s->admitted.empty() || !s->res_admitted.empty() ||
+                    s->res_checked < s->res_published;
         for (auto &l : s->launches) busy |= l.busy;
+        return busy;
+    };
+    while (true) {
+        bool busy = busy_now();
         if (!busy) return DMAS_OK;
         if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
-            busy = !s->queued.empty() || !s->admitted.empty();
-            for (auto &l : s->launches) busy |= l.busy;
+            busy = busy_now();
             if (!busy) return DMAS_OK;
             return srv_fail(DMAS_ERR_TIMEOUT, "timed out draining the server");
         }
@@ -751,13 +1038,16 @@ dmas_status_t dmas_server_stats(dmas_server_t s, dmas_server_stats_t *st)
     st->launches = s->n_launches;
     st->batched_frames = s->n_batched;
     st->queued = (int64_t)s->queued.size();
-    st->admitted_not_launched = (int64_t)s->admitted.size();
+    st->admitted_not_launched = (int64_t)(s->admitted.size() + s->res_admitted.size());
     int64_t inflight = 0;
     for (auto &l : s->launches) inflight += (int64_t)l.frames.size();
+    for (int j = s->res_checked; j < s->res_published; ++j) inflight += s->res_job_frame[j] != nullptr;
     st->in_flight = inflight;
     st->hbm_in_use = (int64_t)s->arena.used();
     st->hbm_peak = (int64_t)s->hbm_peak;
     st->hbm_budget = (int64_t)s->budget;
+    st->resident_launches = s->n_res_launches;
+    st->resident_frames = s->n_res_frames;
     return DMAS_OK;
 }
 
@@ -770,6 +1060,8 @@ dmas_status_t dmas_server_destroy(dmas_server_t s)
         s->worker.join();
     }
     // teardown: failures here have no caller to report to
+    if (s->res_h) __atomic_store_n(&s->res_h->stop, 1, __ATOMIC_RELEASE);   // a running worker exits
+    if (s->res_stream) (void)hipStreamSynchronize(s->res_stream);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamSynchronize(st);
     if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
@@ -783,6 +1075,10 @@ dmas_status_t dmas_server_destroy(dmas_server_t s)
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);
     if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    if (s->res_end) (void)hipEventDestroy(s->res_end);
+    if (s->res_stream) (void)hipStreamDestroy(s->res_stream);
+    if (s->res_d) (void)hipFree(s->res_d);
+    if (s->res_h) (void)hipHostFree(s->res_h);
     for (char *p : s->d_tables) (void)hipFree(p);
     for (char *p : s->h_tables) (void)hipHostFree(p);
     (void)hipFree(s->d_arena);

@@ -59,7 +59,8 @@ class PlanInfo(ctypes.Structure):
 
 class ServerDesc(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("staging_bytes", ctypes.c_int64),
-                ("num_streams", ctypes.c_int32), ("max_batch_frames", ctypes.c_int32)]
+                ("num_streams", ctypes.c_int32), ("max_batch_frames", ctypes.c_int32),
+                ("resident", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FrameInfo(ctypes.Structure):
@@ -74,7 +75,7 @@ class FrameInfo(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "submitted", "completed", "failed", "launches", "batched_frames", "queued", "admitted_not_launched",
-        "in_flight", "hbm_in_use", "hbm_peak", "hbm_budget")]
+        "in_flight", "hbm_in_use", "hbm_peak", "hbm_budget", "resident_launches", "resident_frames")]
 
 
 _lib = None
@@ -326,12 +327,14 @@ class Server:
     ``hbm_budget`` bytes of device memory hold admitted frames' inputs and
     outputs; frames are queued by ``submit`` and launched in multi-frame
     batches of up to ``max_batch`` on ``num_streams`` streams
-    (``max_batch=1, num_streams=1`` gives one plain launch per frame).
+    (``max_batch=1, num_streams=1`` gives one plain launch per frame); with
+    ``resident=True`` the frames that have a resident worker are served by one.
     """
 
-    def __init__(self, hbm_budget: int, staging: int = 0, num_streams: int = 2, max_batch: int = 64):
+    def __init__(self, hbm_budget: int, staging: int = 0, num_streams: int = 2, max_batch: int = 64,
+                 resident: bool = False):
         self._lib = load_library()
-        d = ServerDesc(int(hbm_budget), int(staging), int(num_streams), int(max_batch))
+        d = ServerDesc(int(hbm_budget), int(staging), int(num_streams), int(max_batch), int(bool(resident)), 0)
         self._h = ctypes.c_void_p()
         self._shapes = {}   # ticket -> result shape, for frames whose result stays on the device
         # the library keeps a pointer to each frame's plan: hold the Plan objects until the

@@ -248,3 +248,90 @@ def test_server_holds_its_plans():
         srv.wait(t)
         np.testing.assert_array_equal(srv.fetch(t), ref)
         srv.release(t)
+
+
+# ---------------------------------------------------------------------------
+# Resident workers: a persistent launch per kernel class fed by a job queue
+# ---------------------------------------------------------------------------
+
+def _resident_capable(f):
+    return f.order in (3, 5)
+
+
+def test_resident_equals_alone_bitwise():
+    """Frames served by resident workers (orders 3 and 5; tables of either mode) give the same bits
+    as plain launches, in a mix with frames that go through launches (order 2) and with decimation."""
+    from paper_2511_09165_amd import plan_for_frame
+    rng = np.random.default_rng(31)
+    frames = [_blocker()] + _mix(3, 14)
+    for M, n in [(100, 3), (72, 5)]:          # more than 64 microphones: offsets per microphone block
+        f = synth.random_frame(rng, M, 40, 2048, n)
+        f.env = True
+        frames.append(f)
+    plans = [plan_for_frame(f, env_decimation=(3 if k % 6 == 4 else 1)) for k, f in enumerate(frames)]
+    alone = [_standalone(p, f.x_f32(), f.env) for f, p in zip(frames, plans)]
+    _say(f"resident: {len(frames)} frames")
+    outs, infos, stats = _run_server(frames, plans, hbm_budget=8 << 30, resident=True)
+    for k, (a, b) in enumerate(zip(alone, outs)):
+        assert np.array_equal(a, b), f"frame {k} differs between alone and the resident worker"
+    n_res = sum(_resident_capable(f) for f in frames)
+    assert 0 < n_res < len(frames)
+    assert stats["resident_frames"] == n_res and stats["resident_launches"] >= 1
+    assert stats["completed"] == len(frames) and stats["failed"] == 0
+    for i in infos:
+        assert i["t_arrival"] <= i["t_admit"] <= i["t_launch"] <= i["t_done"]
+    f = frames[1]
+    y_ref = oracle.frame_rows(f, x=f.x_f32().astype(np.float64))
+    if f.env:
+        y_ref = oracle.envelope(y_ref, oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32).astype(np.float64))
+    check_t1(outs[1].astype(np.float64), y_ref)
+    for p in plans:
+        p.close()
+
+
+def test_resident_worker_exits_when_idle_and_relaunches():
+    """A worker that ran out of work exits by itself; the next frame gets a new worker. A plan
+    created after a worker was launched is served by a later worker, with the same bits."""
+    import time
+    from paper_2511_09165_amd import Server, plan_for_frame
+    f = synth.random_frame(np.random.default_rng(41), 32, 300, 4096, 5)
+    g = synth.random_frame(np.random.default_rng(42), 16, 200, 3000, 3)
+    with plan_for_frame(f) as pf:
+        ref_f = _standalone(pf, f.x_f32(), True)
+        _say("resident: idle exit and relaunch")
+        with Server(hbm_budget=1 << 30, resident=True) as srv:
+            t1 = srv.submit(pf, f.x_f32())
+            srv.wait(t1, timeout=60)
+            time.sleep(0.05)                       # well past the idle limit of the worker
+            t2 = srv.submit(pf, f.x_f32())
+            srv.wait(t2, timeout=60)
+            assert srv.stats()["resident_launches"] >= 2
+            with plan_for_frame(g) as pg:          # a plan newer than every worker so far
+                ref_g = _standalone(pg, g.x_f32(), True)
+                t3 = srv.submit(pg, g.x_f32())
+                srv.wait(t3, timeout=60)
+                np.testing.assert_array_equal(srv.fetch(t3), ref_g)
+                srv.release(t3)
+            for t in (t1, t2):
+                np.testing.assert_array_equal(srv.fetch(t), ref_f)
+                srv.release(t)
+            st = srv.stats()
+        assert st["resident_frames"] == 3 and st["failed"] == 0 and st["hbm_in_use"] == 0
+
+
+def test_resident_auto_release_and_drain():
+    """Auto-released frames through resident workers: every record arrives, the arena empties."""
+    from paper_2511_09165_amd import Server, plan_for_frame
+    frames = _mix(8, 10)
+    plans = [plan_for_frame(f) for f in frames]
+    with Server(hbm_budget=2 << 30, resident=True) as srv:
+        for f, p in zip(frames, plans):
+            srv.submit(p, f.x_f32(), envelope=f.env, auto_release=True)
+        srv.drain(120)
+        recs = srv.completed()
+        st = srv.stats()
+    assert len(recs) == len(frames) and all(r["state"] == 3 for r in recs)
+    assert st["hbm_in_use"] == 0 and st["completed"] == len(frames)
+    assert st["resident_frames"] == sum(_resident_capable(f) for f in frames)
+    for p in plans:
+        p.close()
