@@ -395,7 +395,8 @@ def bench_precision(args) -> list:
 
 
 def bench_serving(args) -> list:
-    """Serving: Poisson arrivals of heterogeneous pulse-echo frames, batched server vs one launch per frame.
+    """Serving: Poisson arrivals of heterogeneous pulse-echo frames; batched server, one launch per frame,
+    and resident workers (persistent launches fed by a job queue).
 
     Frames: arrays of 16/32/64 microphones (6-20 cm discs), az/el grids of
     1024-8192 directions, orders 3 and 5, 4096-16384 samples, FP32, envelope
@@ -405,14 +406,18 @@ def bench_serving(args) -> list:
     import synth
     from paper_2511_09165_amd import DmasError, Server, plan_for_frame, server_clock
 
-    pool = synth.serving_pool(n_arrays_per_m=4, max_frames=args.serving_pool)
+    orders = tuple(int(n) for n in args.serving_orders.split(","))
+    pool = synth.serving_pool(n_arrays_per_m=4, max_frames=args.serving_pool, orders=orders)
     plans = [plan_for_frame(f) for f in pool]
     xs = [f.x_f32() for f in pool]
     pix = [f.num_dirs * f.num_samples for f in pool]
     rng = np.random.default_rng(2511091654)
     rates = [float(r) for r in args.serving_rates.split(",")]
     out = []
-    modes = [("batched", dict(num_streams=2, max_batch=64)), ("one_launch_per_frame", dict(num_streams=1, max_batch=1))]
+    all_modes = {"batched": dict(num_streams=2, max_batch=64),
+                 "one_launch_per_frame": dict(num_streams=1, max_batch=1),
+                 "resident": dict(num_streams=2, max_batch=64, resident=True)}
+    modes = [(m, all_modes[m]) for m in args.serving_modes.split(",")]
     for rate in rates:
         n_frames = max(20, int(rate * args.serving_duration))
         gaps = rng.exponential(1.0 / rate, size=n_frames)
@@ -427,7 +432,8 @@ def bench_serving(args) -> list:
                     srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
                 srv.drain(600)
                 srv.completed(100000)
-                launches0 = srv.stats()["launches"]
+                st0 = srv.stats()
+                launches0 = st0["launches"]
                 t0 = server_clock() + 0.05
                 arrivals = t0 + np.cumsum(gaps)
                 busy_retries = 0
@@ -466,6 +472,8 @@ def bench_serving(args) -> list:
                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                         "max_ms": float(lat.max()), "launches": st["launches"] - launches0,
                         "mean_frames_per_launch": len(recs) / max(1, st["launches"] - launches0),
+                        "resident_launches": st["resident_launches"] - st0["resident_launches"],
+                        "resident_frames": st["resident_frames"] - st0["resident_frames"],
                         "hbm_peak_gb": st["hbm_peak"] / 1e9, "busy_retries": busy_retries,
                         "client_late_max_ms": float(max(late)) * 1e3, "slowest": slowest})
             print(json.dumps(out[-1]), flush=True)
@@ -480,6 +488,9 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=200, help="untimed steps first (clocks settle in ~100 ms)")
     ap.add_argument("--serving-rates", default="500,1000,2000,3000,4000", help="offered frames/s (serving)")
+    ap.add_argument("--serving-modes", default="batched,one_launch_per_frame,resident",
+                    help="servers to compare (serving): batched, one_launch_per_frame, resident")
+    ap.add_argument("--serving-orders", default="3,5", help="DMAS orders in the serving pool")
     ap.add_argument("--serving-duration", type=float, default=2.0, help="seconds of arrivals per rate (serving)")
     ap.add_argument("--serving-pool", type=int, default=48, help="distinct frames in the serving pool")
     ap.add_argument("--workload", default="erti32",

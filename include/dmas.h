@@ -227,7 +227,9 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  * worker: one persistent launch per kernel class whose workgroups take work
  * items (a frame's root-plane chunks, then its (tile, segment) workgroups) from
  * a queue of job descriptors that the scheduler writes into pinned host memory
- * while the launch runs, so frames start without a launch each. A worker serves
+ * while the launch runs, so frames start without a launch each; a resident
+ * frame's input is read from the staging memory (coherent in this mode) and
+ * takes no device copy. A worker serves
  * one class and plans created before its launch; a frame of another class or
  * a newer plan lets the worker finish its queue and exit, and the next worker is
  * launched for it. Workers exit after about 7 ms without work, and when the

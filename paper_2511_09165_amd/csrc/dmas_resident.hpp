@@ -13,11 +13,18 @@
 // always end.
 //
 // Memory ordering: the host writes a job, then raises `published` (release);
-// a workgroup that meets a job for the first time performs a system-scope
-// acquire before it reads the job's inputs. After each item every thread
-// performs a system-scope release, then the workgroup counts the item; the
-// workgroup that completes a job stores its `done` flag with system-scope
-// release, so the host can read the job's outputs once it sees the flag.
+// workgroups read job words and the count with system-scope loads, which
+// bypass the caches; a job's input is read from coherent pinned memory. Device
+// memory freed while a worker runs (root planes, outputs) is held back by the
+// host and returned in epochs; a job carries the epoch of its memory, and a
+// workgroup performs one system-scope acquire (dropping stale cache lines) when
+// it first meets a job of a newer epoch than it has seen. Stale lines of a
+// returned range can only predate its return, since no one reads a range while
+// it is free; a launch starts with clean caches. After each item the
+// workgroup's stores reach the L2 and one system-scope release writes the L2
+// back before the item is counted; the workgroup that completes a job stores
+// its `done` flag with system-scope release, so the host can read the job's
+// outputs once it sees the flag.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +45,8 @@ struct ResidentJob {
     int32_t items;           // work items
     int32_t dep;             // roots job this pixels job needs, or -1
     int32_t dep_items;       // items of that roots job
+    int32_t epoch;           // memory epoch of the job's device memory
+    int32_t pad;
     int64_t count;           // roots: samples in the plane
 };
 constexpr int kJobWords = (int)(sizeof(ResidentJob) / 4);
@@ -57,7 +66,9 @@ struct ResidentHost {
 // Device memory, zeroed at the start of a queue generation.
 struct ResidentDevice {
     int32_t cur_job;                   // first job that may have unclaimed items
-    int32_t pad[63];
+    int32_t pub_mirror;                // largest published count read from host memory
+    int32_t stop_mirror;               // 1 once a workgroup has read the stop request
+    int32_t pad[61];
     int32_t claimed[kResidentJobs];    // items handed out per job (may exceed items)
     int32_t finished[kResidentJobs];   // items completed per job
 };
@@ -67,6 +78,7 @@ struct ResidentArgs {
     ResidentDevice *dev;
     int32_t idle_limit;                // empty polls before a workgroup exits
     int32_t dep_limit;                 // polls of a dependency before giving up
+    int32_t epoch0;                    // memory epoch at launch
 };
 
 // Resident worker for one kernel class (nearest delays from tables, plain

@@ -13,30 +13,50 @@ namespace dmas {
 constexpr int32_t kClaimIdle = -1;   // nothing to claim now
 constexpr int32_t kClaimExit = -2;   // nothing to claim and the host asked the workers to stop
 constexpr int kClaimTries = 64;      // jobs passed over per claim before reporting idle
+constexpr int kHostPollEvery = 16;   // idle polls of the device mirrors per read of host memory
 
-__device__ __forceinline__ int32_t load_acquire_sys(const int32_t *p)
+template <typename T>
+__device__ __forceinline__ T load_relaxed_sys(const T *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Thread 0 of a workgroup: the next (job, item), or (kClaimIdle | kClaimExit, 0).
-// pub_seen caches the last published count this workgroup read; jobs below it
-// are complete in host memory. Items are handed out in job order: a job's
+// pub_seen caches the last published count this workgroup knows of; jobs below
+// it are complete in host memory. Items are handed out in job order: a job's
 // counter is raised until it passes the job's item count, then cur_job moves on.
-__device__ __forceinline__ int2 claim_item(const ResidentArgs &a, int &pub_seen)
+// The published count and the stop request are read from host memory only on
+// every kHostPollEvery-th idle poll of a workgroup (poll_host) and are mirrored
+// in device memory for the others. No poll is an acquire (memory epochs order
+// the jobs' device memory).
+__device__ __forceinline__ int2 claim_item(const ResidentArgs &a, int &pub_seen, int &c_job, int &c_items,
+                                           bool poll_host)
 {
     ResidentDevice *dv = a.dev;
     int j = __hip_atomic_load(&dv->cur_job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int tries = 0; tries < kClaimTries; ++tries) {
         if (j >= pub_seen) {
-            // stop first: a stop seen here means every job was published before it
-            const int stop = load_acquire_sys(&a.host->stop);
-            pub_seen = load_acquire_sys(&a.host->published);
-            if (j >= pub_seen) return make_int2(stop ? kClaimExit : kClaimIdle, 0);
+            pub_seen = max(pub_seen, __hip_atomic_load(&dv->pub_mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (j >= pub_seen) {
+                int stop = __hip_atomic_load(&dv->stop_mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (poll_host || stop) {
+                    stop |= load_relaxed_sys(&a.host->stop);
+                    // a stop seen first orders the count after it: the count is final
+                    if (stop) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                    const int pub = load_relaxed_sys(&a.host->published);
+                    __hip_atomic_fetch_max(&dv->pub_mirror, pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (stop) __hip_atomic_store(&dv->stop_mirror, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    pub_seen = max(pub_seen, pub);
+                }
+                if (j >= pub_seen) return make_int2(stop ? kClaimExit : kClaimIdle, 0);
+            }
         }
-        const int items = __hip_atomic_load(&a.host->jobs[j].items, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (j != c_job) {
+            c_job = j;
+            c_items = load_relaxed_sys(&a.host->jobs[j].items);
+        }
         const int i = __hip_atomic_fetch_add(&dv->claimed[j], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (i < items) return make_int2(j, i);
+        if (i < c_items) return make_int2(j, i);
         int expected = j;
         __hip_atomic_compare_exchange_strong(&dv->cur_job, &expected, j + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
@@ -45,17 +65,29 @@ __device__ __forceinline__ int2 claim_item(const ResidentArgs &a, int &pub_seen)
     return make_int2(kClaimIdle, 0);
 }
 
+// Root-plane chunk [item * kRootItem, ...) of a frame whose input x is in host
+// memory: every thread issues its kRootLoads loads before it stores, so the
+// host-memory latency is paid once per item.
+constexpr int kRootLoads = kRootItem / (kDirsPerTile * kWaveSize);
+
 template <int N>
 __device__ __forceinline__ void roots_item(const ResidentJob &jd, int item)
 {
     float2 *plane = const_cast<float2 *>(jd.kp.roots);
-    const int64_t e0 = (int64_t)item * kRootItem;
-    const int64_t e1 = e0 + kRootItem < jd.count ? e0 + kRootItem : jd.count;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const float v = jd.kp.dtype == 0   ? load_sample<0>(jd.kp.x, (size_t)e)
-                        : jd.kp.dtype == 1 ? load_sample<1>(jd.kp.x, (size_t)e)
-                                           : load_sample<2>(jd.kp.x, (size_t)e);
-        plane[e] = make_float2(signed_root<N>(v), v);
+    const int64_t e0 = (int64_t)item * kRootItem + threadIdx.x;
+    float v[kRootLoads];
+#pragma unroll
+    for (int k = 0; k < kRootLoads; ++k) {
+        const int64_t e = e0 + (int64_t)k * (kDirsPerTile * kWaveSize);
+        v[k] = e >= jd.count       ? 0.0f
+               : jd.kp.dtype == 0 ? load_sample<0>(jd.kp.x, (size_t)e)
+               : jd.kp.dtype == 1 ? load_sample<1>(jd.kp.x, (size_t)e)
+                                  : load_sample<2>(jd.kp.x, (size_t)e);
+    }
+#pragma unroll
+    for (int k = 0; k < kRootLoads; ++k) {
+        const int64_t e = e0 + (int64_t)k * (kDirsPerTile * kWaveSize);
+        if (e < jd.count) plane[e] = make_float2(signed_root<N>(v[k]), v[k]);
     }
 }
 
@@ -67,13 +99,14 @@ dmas_resident_kernel(const ResidentArgs a)
     __shared__ int32_t s_cmd[2];
     __shared__ uint32_t s_job[kJobWords];
     const int tid = threadIdx.x;
-    int pub_seen = 0;       // thread 0 only
+    int pub_seen = 0, c_job = -1, c_items = 0;   // thread 0 only
     int have = -1;          // job whose descriptor is in s_job (the same in every thread)
     int dep_ready = -1;     // roots job known complete by this workgroup
+    int seen_epoch = a.epoch0;
     int idle = 0;
     for (;;) {
         if (tid == 0) {
-            const int2 c = claim_item(a, pub_seen);
+            const int2 c = claim_item(a, pub_seen, c_job, c_items, idle % kHostPollEvery == 0);
             s_cmd[0] = c.x;
             s_cmd[1] = c.y;
         }
@@ -89,9 +122,7 @@ dmas_resident_kernel(const ResidentArgs a)
         }
         idle = 0;
         if (job != have) {
-            // first item of this job here: see its inputs (copied by the host or
-            // written by other workgroups) and read its descriptor
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            // first item of this job here: read its descriptor
             const int32_t *src = reinterpret_cast<const int32_t *>(&a.host->jobs[job]);
             for (int w = tid; w < kJobWords; w += blockDim.x)
                 s_job[w] = (uint32_t)__hip_atomic_load(src + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -103,6 +134,11 @@ dmas_resident_kernel(const ResidentArgs a)
         for (int w = 0; w < kJobWords; ++w) words[w] = __builtin_amdgcn_readfirstlane(s_job[w]);
         ResidentJob jd;
         __builtin_memcpy(&jd, words, sizeof jd);
+        if (jd.epoch > seen_epoch) {
+            // the job's device memory was returned after this workgroup last dropped its caches
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            seen_epoch = jd.epoch;
+        }
         if (jd.kind == kJobRoots) {
             roots_item<N>(jd, item);
         } else {
@@ -119,17 +155,18 @@ dmas_resident_kernel(const ResidentArgs a)
                     }
                 }
                 __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // the plane written by other workgroups
                 dep_ready = jd.dep;
             }
             dmas_body<N, CF, ENV, NEAR, DM, kAccF32>(jd.kp, item % jd.kp.num_tiles, item / jd.kp.num_tiles, smem);
         }
-        // this item's stores reach memory before it is counted
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        // this item's stores reach memory before it is counted: every wave waits
+        // for its stores to reach the L2, then one system-scope release writes the
+        // L2 back ahead of the count
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
         if (tid == 0) {
             const int prev =
-                __hip_atomic_fetch_add(&a.dev->finished[job], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&a.dev->finished[job], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             if (prev + 1 == jd.items)
                 __hip_atomic_store(&a.host->done[job], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }

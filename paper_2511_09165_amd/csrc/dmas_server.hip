@@ -11,6 +11,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -114,6 +115,7 @@ struct Frame {
     size_t stage_off = 0;
     bool staged = false;
     size_t in_off = 0, out_off = 0;
+    size_t in_dev_bytes = 0;                 // device copy of the input (none for resident frames)
     size_t plane_bytes = 0, plane_off = 0;   // root plane (plans that stage roots)
     bool on_device = false;
     bool resident = false;   // served by a resident worker
@@ -175,7 +177,8 @@ dmas_status_t srv_fail(dmas_status_t st, const char *msg)
 constexpr int32_t kResidentIdlePolls = 2000;
 constexpr int32_t kResidentDepPolls = 1 << 22;
 constexpr double kResidentLife = 0.020;
-constexpr double kResidentSwitchWait = 0.001;
+constexpr double kResidentSwitchWait = 0.001;   // DMAS_RESIDENT_SWITCH_US overrides
+constexpr double kEpochMin = 0.002;             // shortest memory epoch
 
 // Frames that a resident worker serves: nearest delays from the per-tile
 // tables, plain sums, orders 3 and 5.
@@ -208,6 +211,7 @@ struct dmas_server_s {
     double rate_cap = 3.6e13;   // about 92% of the VALU issue peak of the device
     char *d_arena = nullptr;
     char *h_staging = nullptr;
+    const char *d_staging = nullptr;   // device view of h_staging (resident mode)
     Arena arena, stage_arena;
     size_t hbm_peak = 0;
     hipStream_t copy_stream = nullptr;
@@ -239,6 +243,13 @@ struct dmas_server_s {
     int res_published = 0, res_checked = 0; // jobs written / jobs seen done
     std::vector<Frame *> res_job_frame;     // per job: its frame for a pixels job, else null
     std::deque<Frame *> res_admitted;       // admitted frames for the resident workers
+    std::vector<std::pair<size_t, size_t>> res_held;   // arena ranges freed while the worker runs
+    int64_t res_queued_items = 0;           // pixels items published and not yet done
+    int drain_waiters = 0;                  // threads inside dmas_server_drain
+    int32_t res_epoch = 0;                  // memory epoch (see release_held)
+    double res_t_epoch = 0;
+    double res_switch_wait = kResidentSwitchWait;
+    int64_t res_items_cap = 0;              // bound on res_queued_items (about four device rounds)
     int res_cus = 256;
     int64_t n_res_launches = 0, n_res_frames = 0;
 
@@ -279,13 +290,31 @@ struct dmas_server_s {
         return f->plane_bytes ? reinterpret_cast<float2 *>(d_arena + f->plane_off) : nullptr;
     }
 
+    // Return a frame's device memory. While a resident worker runs, the ranges
+    // are held back and returned in epochs (release_held): the worker drops its
+    // caches once per epoch, not per job.
     void free_device(Frame *f)
     {
         if (!f->on_device) return;
-        arena.release(f->in_off, f->in_bytes);
-        arena.release(f->out_off, f->out_bytes);
-        if (f->plane_bytes) arena.release(f->plane_off, f->plane_bytes);
+        if (f->in_dev_bytes) arena_free(f->in_off, f->in_dev_bytes);
+        arena_free(f->out_off, f->out_bytes);
+        if (f->plane_bytes) arena_free(f->plane_off, f->plane_bytes);
         f->on_device = false;
+    }
+
+    void arena_free(size_t off, size_t bytes)
+    {
+        if (res_running) res_held.emplace_back(off, bytes);
+        else arena.release(off, bytes);
+    }
+
+    void release_held()
+    {
+        if (res_held.empty()) return;
+        for (auto &r : res_held) arena.release(r.first, r.second);
+        res_held.clear();
+        ++res_epoch;   // jobs published from now on may use the returned memory
+        res_t_epoch = now_s();
     }
 
     void free_staging(Frame *f)
@@ -363,32 +392,43 @@ struct dmas_server_s {
         bool progress = false;
         while (!queued.empty()) {
             Frame *f = queued.front();
-            size_t in_off, out_off, plane_off = 0;
-            if (!arena.alloc(f->in_bytes, &in_off)) break;
+            // A resident worker reads the input from the pinned staging memory (in its
+            // roots job), so a resident frame takes device memory for its root plane
+            // and output only, and needs no copy.
+            const bool resident = res_on && resident_capable(f->plan, f->env);
+            const size_t in_dev = resident ? 0 : f->in_bytes;
+            size_t in_off = 0, out_off = 0, plane_off = 0;
+            if (in_dev && !arena.alloc(in_dev, &in_off)) break;
             if (!arena.alloc(f->out_bytes, &out_off)) {
-                arena.release(in_off, f->in_bytes);
+                if (in_dev) arena.release(in_off, in_dev);
                 break;
             }
             if (f->plane_bytes && !arena.alloc(f->plane_bytes, &plane_off)) {
-                arena.release(in_off, f->in_bytes);
+                if (in_dev) arena.release(in_off, in_dev);
                 arena.release(out_off, f->out_bytes);
                 break;
             }
+            f->resident = resident;
+            f->in_dev_bytes = in_dev;
             f->in_off = in_off;
             f->out_off = out_off;
             f->plane_off = plane_off;
             f->on_device = true;
             hbm_peak = std::max(hbm_peak, arena.used());
-            f->copied = get_event();
-            f->resident = res_on && resident_capable(f->plan, f->env);
-            // input copy, then the root plane (resident frames: the worker's), on the copy stream
-            hipError_t e = hipMemcpyAsync(d_arena + in_off, h_staging + f->stage_off, f->in_bytes,
-                                          hipMemcpyHostToDevice, copy_stream);
-            if (e == hipSuccess && f->plane_bytes && !f->resident)
-                e = dmas::stage_roots(f->plan, d_arena + in_off, plane_of(f), copy_stream);
-            if (e == hipSuccess && f->copied) e = hipEventRecord(f->copied, copy_stream);
             f->t_admit = now_s();
             queued.pop_front();
+            if (resident) {
+                f->state = kAdmitted;
+                res_admitted.push_back(f);
+                progress = true;
+                continue;
+            }
+            f->copied = get_event();
+            // input copy, then the root plane, on the copy stream
+            hipError_t e = hipMemcpyAsync(d_arena + in_off, h_staging + f->stage_off, f->in_bytes,
+                                          hipMemcpyHostToDevice, copy_stream);
+            if (e == hipSuccess && f->plane_bytes) e = dmas::stage_roots(f->plan, d_arena + in_off, plane_of(f), copy_stream);
+            if (e == hipSuccess && f->copied) e = hipEventRecord(f->copied, copy_stream);
             if (e != hipSuccess || !f->copied) {
                 (void)hipStreamSynchronize(copy_stream);   // done with the staging and arena ranges
                 fail_unlaunched(f);
@@ -396,7 +436,7 @@ struct dmas_server_s {
                 cv_done.notify_all();
             } else {
                 f->state = kAdmitted;
-                (f->resident ? res_admitted : admitted).push_back(f);
+                admitted.push_back(f);
             }
             progress = true;
         }
@@ -539,6 +579,7 @@ struct dmas_server_s {
     // A frame whose pixels job is done.
     void res_finish(Frame *f)
     {
+        res_queued_items -= dmas::plan_workgroups(f->plan, f->env);
         const bool ok = __atomic_load_n(&res_h->error, __ATOMIC_ACQUIRE) == 0;
         f->t_done = now_s();
         f->state = ok ? kDone : kFailed;
@@ -566,6 +607,7 @@ struct dmas_server_s {
         for (int j = res_checked; j < res_published; ++j)
             if (Frame *f = res_job_frame[j]) fail_unlaunched(f);
         res_checked = res_published;
+        res_queued_items = 0;
     }
 
     // Launch a worker for the current class; reset starts a new queue
@@ -583,12 +625,15 @@ struct dmas_server_s {
             res_job_frame.clear();
         }
         __atomic_store_n(&res_h->stop, 0, __ATOMIC_RELEASE);
+        if (!reset && e == hipSuccess)
+            e = hipMemsetAsync(&res_d->stop_mirror, 0, sizeof(int32_t), res_stream);
         res_serial = dmas::plan_serials().load();
-        const dmas::ResidentArgs a{res_hd, res_d, kResidentIdlePolls, kResidentDepPolls};
+        const dmas::ResidentArgs a{res_hd, res_d, kResidentIdlePolls, kResidentDepPolls, res_epoch};
         int blocks = 0;
         if (e == hipSuccess)
             e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, 0, res_lds, res_stream, &blocks);
         if (e == hipSuccess && blocks < 1) e = hipErrorInvalidConfiguration;
+        res_items_cap = (int64_t)4 * blocks * res_cus;
         if (e == hipSuccess)
             e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, (unsigned)(blocks * res_cus),
                                       res_lds, res_stream, nullptr);
@@ -609,8 +654,8 @@ struct dmas_server_s {
     void res_publish(Frame *f)
     {
         const dmas::KernelParams kp = dmas::make_params(
-            f->plan, d_arena + f->in_off, plane_of(f), reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale,
-            f->env);
+            f->plan, d_staging + f->stage_off, plane_of(f), reinterpret_cast<float *>(d_arena + f->out_off),
+            f->in_scale, f->env);
         int dep = -1, dep_items = 0;
         if (f->plane_bytes) {
             dmas::ResidentJob &r = res_h->jobs[res_published];
@@ -620,6 +665,8 @@ struct dmas_server_s {
             r.items = (int32_t)((r.count + dmas::kRootItem - 1) / dmas::kRootItem);
             r.dep = -1;
             r.dep_items = 0;
+            r.epoch = res_epoch;
+            r.pad = 0;
             dep = res_published;
             dep_items = r.items;
             res_job_frame.push_back(nullptr);
@@ -632,8 +679,11 @@ struct dmas_server_s {
         j.items = (int32_t)dmas::plan_workgroups(f->plan, f->env);
         j.dep = dep;
         j.dep_items = dep_items;
+        j.epoch = res_epoch;
+        j.pad = 0;
         res_job_frame.push_back(f);
         ++res_published;
+        res_queued_items += j.items;
         __atomic_store_n(&res_h->published, res_published, __ATOMIC_RELEASE);
         f->state = kLaunched;
         f->t_launch = now_s();
@@ -662,6 +712,7 @@ struct dmas_server_s {
             if (q != hipErrorNotReady) {
                 res_running = false;
                 res_stopping = false;
+                release_held();
                 progress = true;
                 if (q != hipSuccess) res_fail_outstanding(hipGetErrorString(q));
                 // a worker that ended has completed every job it claimed: read the flags again
@@ -681,18 +732,6 @@ struct dmas_server_s {
         double oldest_other = -1;   // admission time of the oldest frame the worker cannot take
         for (auto it = res_admitted.begin(); it != res_admitted.end();) {
             Frame *f = *it;
-            const hipError_t q = hipEventQuery(f->copied);
-            if (q == hipErrorNotReady) {
-                ++it;
-                continue;
-            }
-            if (q != hipSuccess) {
-                it = res_admitted.erase(it);
-                fail_unlaunched(f);
-                worker_error = "input copy failed";
-                progress = true;
-                continue;
-            }
             if (!res_running && !res_stopping && res_checked == res_published) {
                 // no worker: launch one for this frame's class with the largest LDS that the
                 // class's admitted frames need
@@ -716,6 +755,7 @@ struct dmas_server_s {
             const bool fits = (can_take || (res_running && !res_stopping && t_now - res_t_launch < kResidentLife)) &&
                               res_same_class(f) && lds <= res_lds && f->plan->serial < res_serial &&
                               res_published + 2 <= dmas::kResidentJobs;
+            if (fits && res_queued_items >= res_items_cap) break;   // queue deep enough: keep arrival order
             if (fits) {
                 it = res_admitted.erase(it);
                 res_publish(f);
@@ -725,13 +765,20 @@ struct dmas_server_s {
                 ++it;
             }
         }
+        // held memory goes back when frames wait for memory or a drain waits for it
+        if (res_running && !res_held.empty() && (!queued.empty() || drain_waiters > 0) &&
+            t_now - res_t_epoch >= kEpochMin) {
+            release_held();
+            progress = true;
+        }
         // let the worker finish its queue and exit when a frame it cannot take has waited,
         // when it has nothing left, when it has run its time, or when launches wait for the device
         if (res_running && !res_stopping) {
             const bool idle = res_checked == res_published;
             bool launches_wait = !admitted.empty();
             for (auto &l : launches) launches_wait |= l.busy;
-            if ((oldest_other >= 0 && (idle || t_now - oldest_other > kResidentSwitchWait)) ||
+
+            if ((oldest_other >= 0 && (idle || t_now - oldest_other > res_switch_wait)) ||
                 t_now - res_t_launch >= kResidentLife || launches_wait || res_published + 2 > dmas::kResidentJobs) {
                 __atomic_store_n(&res_h->stop, 1, __ATOMIC_RELEASE);
                 res_stopping = true;
@@ -818,8 +865,16 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
     };
     hipError_t e = hipMalloc(&s->d_arena, s->budget);
     if (e != hipSuccess) return fail_all(e, "HBM arena");
-    e = hipHostMalloc(&s->h_staging, s->staging, hipHostMallocDefault);
+    // resident workers read frames' inputs from the staging memory itself: coherent there
+    e = hipHostMalloc(&s->h_staging, s->staging,
+                      d->resident ? (hipHostMallocCoherent | hipHostMallocMapped) : hipHostMallocDefault);
     if (e != hipSuccess) return fail_all(e, "pinned staging");
+    if (d->resident) {
+        void *dv = nullptr;
+        if ((e = hipHostGetDevicePointer(&dv, s->h_staging, 0)) != hipSuccess)
+            return fail_all(e, "pinned staging (device view)");
+        s->d_staging = static_cast<const char *>(dv);
+    }
     s->arena.reset(s->budget);
     s->stage_arena.reset(s->staging);
     e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
@@ -847,6 +902,7 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *d, dmas_server_t *out
     if ((e = hipMemcpyAsync(s->d_tables[0], s->h_tables[0], kAlign, hipMemcpyHostToDevice, s->copy_stream)) != hipSuccess)
         return fail_all(e, "copy stream warm-up");
     if (d->resident) {
+        if (const char *sw = std::getenv("DMAS_RESIDENT_SWITCH_US")) s->res_switch_wait = std::max(0.0, std::atof(sw)) * 1e-6;
         // the job queue in coherent pinned memory (polled by the device), the claim
         // counters on the device
         s->res_on = true;
@@ -1013,10 +1069,15 @@ dmas_status_t dmas_server_drain(dmas_server_t s, double timeout)
     const auto deadline = deadline_after(timeout);
     auto busy_now = [s] {
         bool busy = !s->queued.empty() || !s->admitted.empty() || !s->res_admitted.empty() ||
-                    s->res_checked < s->res_published;
+                    s->res_checked < s->res_published || !s->res_held.empty();
         for (auto &l : s->launches) busy |= l.busy;
         return busy;
     };
+    struct Waiter {   // counted while waiting (under mu): an idle worker exits for a drain
+        int &n;
+        explicit Waiter(int &c) : n(c) { ++n; }
+        ~Waiter() { --n; }
+    } waiter(s->drain_waiters);
     while (true) {
         bool busy = busy_now();
         if (!busy) return DMAS_OK;
