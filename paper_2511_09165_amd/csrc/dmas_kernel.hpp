@@ -418,8 +418,11 @@ __device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const 
 // (batched) kernels, so a pixel's arithmetic does not depend on how it was
 // launched.
 template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
+// tx is the thread's index in the workgroup; a caller that runs the body in a
+// loop passes a value the compiler cannot see through, so that nothing derived
+// from it is kept live across iterations.
 __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile, const int seg,
-                                          float *__restrict__ smem)
+                                          float *__restrict__ smem, const int tx = (int)threadIdx.x)
 {
     constexpr bool LINEAR = DM == kDelayLinear;
     constexpr bool TAB = DM == kDelayTable;          // tables through the scalar cache
@@ -428,8 +431,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     constexpr int K = kSamplesPerLane;
     constexpr int C = kChunk;
 
-    const int lane = threadIdx.x & (kWaveSize - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    const int lane = tx & (kWaveSize - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tx / kWaveSize);
 
     constexpr bool ROOTS = kStagesRoots<N, LINEAR>;
     using Elem = typename std::conditional<ROOTS, float2, float>::type;
@@ -553,7 +556,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     if (all_mics) block_geometry(0);
     if constexpr (ENV) {
         for (int i = lane; i < ring_stride(H); i += kWaveSize) ring[i] = 0.0f;
-        for (int j = threadIdx.x; j < env_taps_len(H); j += W * kWaveSize) {
+        for (int j = tx; j < env_taps_len(H); j += W * kWaveSize) {
             const int k = j - kTapLead;   // reversed: entry kTapLead + k holds h[2H - k]
             tap_lds[j] = (k >= 0 && k <= 2 * H) ? taps[2 * H - k] : 0.0f;
         }

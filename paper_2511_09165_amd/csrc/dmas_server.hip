@@ -119,6 +119,7 @@ struct Frame {
     size_t plane_bytes = 0, plane_off = 0;   // root plane (plans that stage roots)
     bool on_device = false;
     bool resident = false;   // served by a resident worker
+    int res_roots_job = -1, res_roots_items = 0;   // its roots job in the worker's queue
     hipEvent_t copied = nullptr;
     int state = kQueued;
     int batch_frames = 0;
@@ -249,7 +250,7 @@ struct dmas_server_s {
     int32_t res_epoch = 0;                  // memory epoch (see release_held)
     double res_t_epoch = 0;
     double res_switch_wait = kResidentSwitchWait;
-    int64_t res_items_cap = 0;              // bound on res_queued_items (about four device rounds)
+    int64_t res_items_cap = 0;              // bound on res_queued_items (about eight device rounds)
     int res_cus = 256;
     int64_t n_res_launches = 0, n_res_frames = 0;
 
@@ -633,7 +634,7 @@ struct dmas_server_s {
         if (e == hipSuccess)
             e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, 0, res_lds, res_stream, &blocks);
         if (e == hipSuccess && blocks < 1) e = hipErrorInvalidConfiguration;
-        res_items_cap = (int64_t)4 * blocks * res_cus;
+        res_items_cap = (int64_t)8 * blocks * res_cus;
         if (e == hipSuccess)
             e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, (unsigned)(blocks * res_cus),
                                       res_lds, res_stream, nullptr);
@@ -650,45 +651,56 @@ struct dmas_server_s {
         return true;
     }
 
-    // Write a frame's jobs (roots, then pixels) and publish them.
-    void res_publish(Frame *f)
+    // Write and publish a frame's roots job (frames with a root plane); its
+    // pixels job follows in res_publish_pixels, after the next frame's roots job
+    // when several frames are published together, so that a root plane is being
+    // filled while the previous frame's pixels run.
+    void res_publish_roots(Frame *f)
     {
-        const dmas::KernelParams kp = dmas::make_params(
-            f->plan, d_staging + f->stage_off, plane_of(f), reinterpret_cast<float *>(d_arena + f->out_off),
-            f->in_scale, f->env);
-        int dep = -1, dep_items = 0;
-        if (f->plane_bytes) {
-            dmas::ResidentJob &r = res_h->jobs[res_published];
-            r.kp = kp;
-            r.kind = dmas::kJobRoots;
-            r.count = (int64_t)f->plan->M * f->plan->T;
-            r.items = (int32_t)((r.count + dmas::kRootItem - 1) / dmas::kRootItem);
-            r.dep = -1;
-            r.dep_items = 0;
-            r.epoch = res_epoch;
-            r.pad = 0;
-            dep = res_published;
-            dep_items = r.items;
-            res_job_frame.push_back(nullptr);
-            ++res_published;
-        }
+        f->res_roots_job = -1;
+        f->res_roots_items = 0;
+        f->state = kLaunched;
+        f->t_launch = now_s();
+        f->batch_frames = 1;
+        ++n_res_frames;
+        if (!f->plane_bytes) return;
+        dmas::ResidentJob &r = res_h->jobs[res_published];
+        r.kp = res_params(f);
+        r.kind = dmas::kJobRoots;
+        r.count = (int64_t)f->plan->M * f->plan->T;
+        r.items = (int32_t)((r.count + dmas::kRootItem - 1) / dmas::kRootItem);
+        r.dep = -1;
+        r.dep_items = 0;
+        r.epoch = res_epoch;
+        r.pad = 0;
+        f->res_roots_job = res_published;
+        f->res_roots_items = r.items;
+        res_job_frame.push_back(nullptr);
+        ++res_published;
+        __atomic_store_n(&res_h->published, res_published, __ATOMIC_RELEASE);
+    }
+
+    void res_publish_pixels(Frame *f)
+    {
         dmas::ResidentJob &j = res_h->jobs[res_published];
-        j.kp = kp;
+        j.kp = res_params(f);
         j.kind = dmas::kJobPixels;
         j.count = 0;
         j.items = (int32_t)dmas::plan_workgroups(f->plan, f->env);
-        j.dep = dep;
-        j.dep_items = dep_items;
+        j.dep = f->res_roots_job;
+        j.dep_items = f->res_roots_items;
         j.epoch = res_epoch;
         j.pad = 0;
         res_job_frame.push_back(f);
         ++res_published;
         res_queued_items += j.items;
         __atomic_store_n(&res_h->published, res_published, __ATOMIC_RELEASE);
-        f->state = kLaunched;
-        f->t_launch = now_s();
-        f->batch_frames = 1;
-        ++n_res_frames;
+    }
+
+    dmas::KernelParams res_params(const Frame *f) const
+    {
+        return dmas::make_params(f->plan, d_staging + f->stage_off, plane_of(f),
+                                 reinterpret_cast<float *>(d_arena + f->out_off), f->in_scale, f->env);
     }
 
     bool res_same_class(const Frame *f) const
@@ -730,6 +742,7 @@ struct dmas_server_s {
         const double t_now = now_s();
         const bool can_take = res_running && !res_stopping && t_now - res_t_launch < kResidentLife;
         double oldest_other = -1;   // admission time of the oldest frame the worker cannot take
+        Frame *pending = nullptr;   // roots published, pixels not yet
         for (auto it = res_admitted.begin(); it != res_admitted.end();) {
             Frame *f = *it;
             if (!res_running && !res_stopping && res_checked == res_published) {
@@ -754,17 +767,20 @@ struct dmas_server_s {
             const size_t lds = f->env ? f->plan->lds_env : f->plan->lds_rf;
             const bool fits = (can_take || (res_running && !res_stopping && t_now - res_t_launch < kResidentLife)) &&
                               res_same_class(f) && lds <= res_lds && f->plan->serial < res_serial &&
-                              res_published + 2 <= dmas::kResidentJobs;
+                              res_published + 3 <= dmas::kResidentJobs;
             if (fits && res_queued_items >= res_items_cap) break;   // queue deep enough: keep arrival order
             if (fits) {
                 it = res_admitted.erase(it);
-                res_publish(f);
+                res_publish_roots(f);
+                if (pending) res_publish_pixels(pending);
+                pending = f;
                 progress = true;
             } else {
                 if (oldest_other < 0) oldest_other = f->t_admit;
                 ++it;
             }
         }
+        if (pending) res_publish_pixels(pending);
         // held memory goes back when frames wait for memory or a drain waits for it
         if (res_running && !res_held.empty() && (!queued.empty() || drain_waiters > 0) &&
             t_now - res_t_epoch >= kEpochMin) {
