@@ -232,8 +232,9 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  * takes no device copy. A worker serves
  * one class and plans created before its launch; a frame of another class or
  * a newer plan lets the worker finish its queue and exit, and the next worker is
- * launched for it. Workers exit after about 7 ms without work, and when the
- * server is destroyed. While a worker runs it holds the compute units it was
+ * launched for it (after DMAS_RESIDENT_SWITCH_US microseconds of waiting,
+ * default 1000, read at server creation; at once when the worker is idle).
+ * Workers exit after about 7 ms without work, and when the server is destroyed. While a worker runs it holds the compute units it was
  * launched on, so other kernels on the device (other frames' launches, plan
  * creation) start when it exits.
  * Each frame's pixels are computed by the same device code as

@@ -335,3 +335,27 @@ def test_resident_auto_release_and_drain():
     assert st["resident_frames"] == sum(_resident_capable(f) for f in frames)
     for p in plans:
         p.close()
+
+
+def test_resident_destroy_with_frames_in_flight():
+    """Closing a resident server with frames still queued or running returns promptly: the worker
+    finishes what it has claimed and exits; a new server afterwards serves frames normally."""
+    import time
+    from paper_2511_09165_amd import Server, plan_for_frame
+    frames = _mix(9, 8)
+    plans = [plan_for_frame(f) for f in frames]
+    _say("resident: destroy with frames in flight")
+    t0 = time.time()
+    with Server(hbm_budget=2 << 30, resident=True) as srv:
+        for f, p in zip(frames, plans):
+            srv.submit(p, f.x_f32(), envelope=f.env)
+    assert time.time() - t0 < 30
+    f, p = frames[0], plans[0]
+    ref = _standalone(p, f.x_f32(), f.env)
+    with Server(hbm_budget=1 << 30, resident=True) as srv:
+        t = srv.submit(p, f.x_f32(), envelope=f.env)
+        srv.wait(t, timeout=60)
+        np.testing.assert_array_equal(srv.fetch(t), ref)
+        srv.release(t)
+    for q in plans:
+        q.close()
