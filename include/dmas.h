@@ -66,7 +66,7 @@ typedef struct dmas_plan_s *dmas_plan_t;
 typedef enum {
     DMAS_OK = 0,
     DMAS_ERR_INVALID_ARG = 1,   /* bad pointer, size, order or flag */
-    DMAS_ERR_UNSUPPORTED = 2,   /* valid request this build does not serve */
+    DMAS_ERR_UNSUPPORTED = 2,   /* valid request the library does not serve */
     DMAS_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
     DMAS_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
     DMAS_ERR_BUSY = 5,          /* serving: staging memory full, submit again later */
