@@ -250,7 +250,7 @@ struct dmas_server_s {
     int32_t res_epoch = 0;                  // memory epoch (see release_held)
     double res_t_epoch = 0;
     double res_switch_wait = kResidentSwitchWait;
-    int64_t res_items_cap = 0;              // bound on res_queued_items (about eight device rounds)
+    int64_t res_items_cap = 0;              // bound on res_queued_items (about sixteen device rounds)
     int res_cus = 256;
     int64_t n_res_launches = 0, n_res_frames = 0;
 
@@ -634,7 +634,7 @@ struct dmas_server_s {
         if (e == hipSuccess)
             e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, 0, res_lds, res_stream, &blocks);
         if (e == hipSuccess && blocks < 1) e = hipErrorInvalidConfiguration;
-        res_items_cap = (int64_t)8 * blocks * res_cus;
+        res_items_cap = (int64_t)16 * blocks * res_cus;
         if (e == hipSuccess)
             e = dmas::launch_resident(res_order, res_cf, res_env, res_near, res_delay, a, (unsigned)(blocks * res_cus),
                                       res_lds, res_stream, nullptr);
@@ -823,7 +823,8 @@ struct dmas_server_s {
                     cv_work.wait_for(lk, std::chrono::milliseconds(5));
                 } else {
                     lk.unlock();
-                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                    // a resident worker waits on this loop for new jobs: poll faster
+                    std::this_thread::sleep_for(std::chrono::microseconds(res_running ? 5 : 20));
                     lk.lock();
                 }
             }
