@@ -568,6 +568,40 @@ def test_random_configurations(seed):
     check_t1(env, env_ref)
 
 
+@pytest.mark.parametrize("seed", list(range(12)))
+def test_random_storage_and_precision(seed):
+    """Random plans over input storage (FP32, FP16 with a power-of-two scale, BF16) and FP64
+    Newton-Girard, with random sizes, order, CF, geometry, delay mode, FIR length and decimation:
+    image and envelope within T1 of the oracle on the dequantised input."""
+    rng = np.random.default_rng(7000 + seed)
+    M = int(rng.integers(2, 90))
+    n = int(rng.integers(2, min(8, M) + 1))
+    near = bool(rng.random() < 0.3)
+    f = synth.random_frame(rng, M, int(rng.integers(1, 150)), int(rng.integers(1, 2000)), n, nearfield=near)
+    f.use_cf = bool(rng.random() < 0.8)
+    linear = bool(f.use_cf and rng.random() < 0.25)
+    dtype = str(rng.choice(["f32", "f16", "bf16"]))
+    ng = bool(rng.random() < 0.5)
+    L = int(rng.choice([1, 7, 63]))
+    dec = int(rng.choice([1, 2, 5]))
+    taps = rng.normal(size=L).astype(np.float32)
+    _say(f"random storage #{seed}: M={M} D={f.num_dirs} T={f.num_samples} n={n} cf={f.use_cf} near={near} "
+         f"linear={linear} dtype={dtype} ng_fp64={ng} L={L} dec={dec}")
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    amax = float(np.abs(f.x).max())
+    scale = 2.0 ** np.floor(np.log2(amax / 16384.0)) if dtype == "f16" else 1.0
+    xq = torch.from_numpy(f.x / scale).to(tdt)
+    x_deq = xq.float().numpy().astype(np.float64) * scale
+    with _plan(f, in_dtype=dtype, ng_fp64=ng, linear=linear, fir_taps=taps, env_decimation=dec) as plan:
+        xd = xq.cuda()
+        y = plan.beamform(xd, in_scale=scale).cpu().numpy().astype(np.float64)
+        env = plan.envelope(xd, in_scale=scale).cpu().numpy().astype(np.float64)
+    y_ref = oracle.frame_rows(f, x=x_deq, interp=linear)
+    env_ref = oracle.envelope(y_ref, taps.astype(np.float64))[:, ::dec]
+    check_t1(y, y_ref)
+    check_t1(env, env_ref)
+
+
 def test_bad_output_buffers_rejected():
     """Output tensors of the wrong shape, type, layout or device are refused before any launch."""
     f = synth.random_frame(np.random.default_rng(97), 8, 5, 100, 2)
