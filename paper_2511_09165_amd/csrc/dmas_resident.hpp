@@ -21,10 +21,11 @@
 // it first meets a job of a newer epoch than it has seen. Stale lines of a
 // returned range can only predate its return, since no one reads a range while
 // it is free; a launch starts with clean caches. After each item the
-// workgroup's stores reach the L2 and one system-scope release writes the L2
-// back before the item is counted; the workgroup that completes a job stores
-// its `done` flag with system-scope release, so the host can read the job's
-// outputs once it sees the flag.
+// workgroup's stores reach the L2; when the workgroup leaves a job, one
+// system-scope release writes the L2 back before its items of that job are
+// counted. The workgroup that completes a job stores its `done` flag with
+// system-scope release, so the host can read the job's outputs once it sees
+// the flag.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -104,6 +104,21 @@ dmas_resident_kernel(const ResidentArgs a)
     int dep_ready = -1;     // roots job known complete by this workgroup
     int seen_epoch = a.epoch0;
     int idle = 0;
+    // items of one job completed here and not yet counted (the same in every thread)
+    int cnt_job = -1, cnt_n = 0, cnt_items = 0;
+    // Count them: their stores have reached the L2 (each item waits for its own),
+    // one system-scope release writes the L2 back ahead of the count, and the
+    // workgroup that completes the job raises its done flag.
+    auto flush_count = [&]() {
+        if (cnt_n == 0) return;
+        if (tid == 0) {
+            const int prev =
+                __hip_atomic_fetch_add(&a.dev->finished[cnt_job], cnt_n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (prev + cnt_n == cnt_items)
+                __hip_atomic_store(&a.host->done[cnt_job], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        cnt_n = 0;
+    };
     for (;;) {
         if (tid == 0) {
             const int2 c = claim_item(a, pub_seen, c_job, c_items, idle % kHostPollEvery == 0);
@@ -114,6 +129,9 @@ dmas_resident_kernel(const ResidentArgs a)
         const int job = __builtin_amdgcn_readfirstlane(s_cmd[0]);
         const int item = __builtin_amdgcn_readfirstlane(s_cmd[1]);
         __syncthreads();   // every thread has read s_cmd before thread 0 writes it again
+        // a workgroup moving on from a job (or going idle) counts what it did there
+        // first, so no wait on a job's completion can depend on an uncounted item
+        if (job != cnt_job) flush_count();
         if (job == kClaimExit) break;
         if (job == kClaimIdle) {
             if (++idle > a.idle_limit) break;
@@ -163,17 +181,13 @@ dmas_resident_kernel(const ResidentArgs a)
             asm volatile("" : "+v"(tx));
             dmas_body<N, CF, ENV, NEAR, DM, kAccF32>(jd.kp, item % jd.kp.num_tiles, item / jd.kp.num_tiles, smem, tx);
         }
-        // this item's stores reach memory before it is counted: every wave waits
-        // for its stores to reach the L2, then one system-scope release writes the
-        // L2 back ahead of the count
+        // every wave waits for this item's stores to reach the L2; the item is
+        // counted when the workgroup leaves the job
         __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
-        if (tid == 0) {
-            const int prev =
-                __hip_atomic_fetch_add(&a.dev->finished[job], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (prev + 1 == jd.items)
-                __hip_atomic_store(&a.host->done[job], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        cnt_job = job;
+        cnt_items = jd.items;
+        ++cnt_n;
     }
 }
 
