@@ -177,7 +177,7 @@ dmas_status_t srv_fail(dmas_status_t st, const char *msg)
 // of another class waits before the worker is asked to exit.
 constexpr int32_t kResidentIdlePolls = 2000;
 constexpr int32_t kResidentDepPolls = 1 << 22;
-constexpr double kResidentLife = 0.020;
+constexpr double kResidentLife = 0.100;
 constexpr double kResidentSwitchWait = 0.001;   // DMAS_RESIDENT_SWITCH_US overrides
 constexpr double kEpochMin = 0.002;             // shortest memory epoch
 
