@@ -234,7 +234,10 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  * a newer plan lets the worker finish its queue and exit, and the next worker is
  * launched for it (after DMAS_RESIDENT_SWITCH_US microseconds of waiting,
  * default 1000, read at server creation; at once when the worker is idle).
- * Workers exit after about 7 ms without work, and when the server is destroyed. While a worker runs it holds the compute units it was
+ * Workers exit after about 7 ms without work, and when the server is destroyed.
+ * While a worker runs, the device memory of finished frames returns to the
+ * budget in epochs (at least 2 ms apart, when frames wait for memory or a
+ * drain waits), so hbm_in_use can include it for that long. While a worker runs it holds the compute units it was
  * launched on, so other kernels on the device (other frames' launches, plan
  * creation) start when it exits.
  * Each frame's pixels are computed by the same device code as
