@@ -359,3 +359,31 @@ def test_resident_destroy_with_frames_in_flight():
         srv.release(t)
     for q in plans:
         q.close()
+
+
+def test_resident_half_precision_inputs_bitwise():
+    """FP16 and BF16 frames through resident workers (the roots job reads 16-bit samples from the
+    staging memory) give the same bits as plain launches, next to FP32 frames."""
+    from paper_2511_09165_amd import Server, plan_for_frame
+    rng = np.random.default_rng(51)
+    cases = []
+    for k, (dtype, n) in enumerate([("f16", 3), ("bf16", 5), ("f32", 5), ("bf16", 3), ("f16", 5)]):
+        f = synth.random_frame(rng, int(rng.choice([16, 32, 72])), int(rng.integers(20, 200)),
+                               int(rng.choice([900, 2048])), n)
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+        scale = 2.0 ** -8 if dtype == "f16" else 1.0
+        xq = torch.from_numpy(f.x / scale).to(tdt)
+        host = xq.view(torch.int16).numpy().view(np.uint16) if dtype == "bf16" else xq.numpy()
+        plan = plan_for_frame(f, in_dtype=dtype)
+        ref = plan.envelope(xq.cuda(), in_scale=scale).cpu().numpy()
+        cases.append((plan, host, scale, ref))
+    _say("resident: FP16/BF16 frames")
+    with Server(hbm_budget=1 << 30, resident=True) as srv:
+        tickets = [srv.submit(p, h, in_scale=s) for p, h, s, _ in cases]
+        for t, (p, _, _, ref) in zip(tickets, cases):
+            srv.wait(t, timeout=60)
+            np.testing.assert_array_equal(srv.fetch(t), ref)
+            srv.release(t)
+        assert srv.stats()["resident_frames"] == len(cases)
+    for p, _, _, _ in cases:
+        p.close()
