@@ -9,10 +9,14 @@ sums, Newton-Girard, coherence factor, envelope FIR and store, all in one
 kernel. Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: throughput in direction*samples/s, the dominant kernel's
-roofline position (VALU issue bound), and the FP64 CPU oracle timed on a
-sample of the same workload.
+roofline position (VALU issue bound; the envelope FIR, which runs on the matrix
+cores, as its own leg), the FP64 CPU oracle timed on a sample of the same
+workload, a short serving run (Poisson arrivals of mixed frames at 2000
+frames/s: p50/p99 frame latency beside throughput), and the same frame and the
+1024-microphone near-field frame with steering delays evaluated on the device
+instead of read from the plan's tables.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serving]
 """
 
 from __future__ import annotations
@@ -64,16 +68,22 @@ def root_slots(n: int) -> int:
     return 0 if n == 1 else (TRANS_SLOTS + 1 if n == 2 else 2 * TRANS_SLOTS + 2)
 
 
-def pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
-    """Slots per output pixel: microphone loop + Newton-Girard + CF + envelope FIR."""
+def pixel_slots(M: int, n: int, cf: bool) -> int:
+    """VALU slots per output pixel: microphone loop + Newton-Girard + CF + scale. The envelope FIR
+    runs on the matrix cores and is counted apart (``fir_flops``)."""
     ng = {1: 0, 2: 3, 3: 7, 4: 11, 5: 15, 6: 21, 7: 28, 8: 36}[n]
     cf_ops = (4 + TRANS_SLOTS) if cf else 0      # square, fma, rcp, 2 mul
-    return M * mic_slots(n, cf) + ng + cf_ops + 1 + fir_len
+    return M * mic_slots(n, cf) + ng + cf_ops + 1
 
 
-def launch_slots(M: int, T: int, D: int, n: int, cf: bool, fir_len: int) -> int:
-    """Algorithmic slots of one frame: every pixel, plus every channel sample's root."""
-    return D * T * pixel_slots(M, n, cf, fir_len) + M * T * root_slots(n)
+def launch_slots(M: int, T: int, D: int, n: int, cf: bool) -> int:
+    """Algorithmic VALU slots of one frame: every pixel, plus every channel sample's root."""
+    return D * T * pixel_slots(M, n, cf) + M * T * root_slots(n)
+
+
+def fir_flops(D: int, T_out: int, fir_len: int) -> float:
+    """Algorithmic flops of the envelope FIR: fir_len multiply-adds (2 flops) per output."""
+    return 2.0 * D * T_out * fir_len
 
 
 def _code_only(text: str) -> str:
@@ -186,13 +196,25 @@ def _timed(launch, steps: int, warmup: int, stream):
     return wall * 1e3 / steps, ev0.elapsed_time(ev1) / steps
 
 
-def _roofline(slots: int, pixels: int, kernel_ms: float, traffic=None) -> dict:
+def _roofline(slots: int, pixels: int, kernel_ms: float, traffic=None, fir=None) -> dict:
     """VALU-issue roofline of one step: ``slots`` algorithmic slots over the step's kernel time
-    (root pass + beamformer, HIP events on the launch stream)."""
+    (root pass + beamformer, HIP events on the launch stream). ``fir`` = flops of the envelope FIR,
+    which runs on the matrix cores, reported against the FP32 matrix-core peak over the same time."""
     achieved = slots / (kernel_ms * 1e-3)
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12, "unit": "TOP/s",
-            "frac": achieved / VALU_SLOTS_PER_S, "traffic": traffic, "kernel_ms": kernel_ms,
-            "ops_per_pixel": slots / pixels, "op": "VALU lane-instruction issue slot (transcendental = 2)"}
+    rec = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOTS_PER_S / 1e12, "unit": "TOP/s",
+           "frac": achieved / VALU_SLOTS_PER_S, "traffic": traffic, "kernel_ms": kernel_ms,
+           "ops_per_pixel": slots / pixels,
+           "op": "VALU lane-instruction issue slot (transcendental = 2); the envelope FIR is not in this count"}
+    if traffic is not None:
+        rec["traffic_source"] = ("replayed: HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / "
+                                 "WRITE_SIZE record (profiles/dmas_envelope_order5_erti32_traffic.txt), "
+                                 "valid while the kernel source hashes to the recorded value")
+    if fir is not None:
+        fa = fir / (kernel_ms * 1e-3)
+        rec["mfma_fir"] = {"bound": "mfma", "achieved": fa / 1e12, "peak": MFMA_F32_FLOPS / 1e12,
+                           "unit": "TFLOP/s", "frac": fa / MFMA_F32_FLOPS, "flops_per_pixel": fir / pixels,
+                           "op": "envelope FIR multiply-add (2 flops) on the FP32 matrix cores, same step time"}
+    return rec
 
 
 def _base_record(args, value, ms_per_step, dtype, config) -> dict:
@@ -200,6 +222,43 @@ def _base_record(args, value, ms_per_step, dtype, config) -> dict:
             "unit": "direction*samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": dtype, "data": "synthetic (seeded)", "config": config}
+
+
+def _settle(launch, stream, ms: float = 250.0) -> int:
+    """Untimed launches until ``ms`` of device time have passed, so the GPU clocks have ramped up
+    before the warmup steps (a handful of steps after plan creation still runs at lower clocks).
+    Returns the number of launches (reported in the JSON line as clock_settle)."""
+    import torch
+    done, t0 = 0, time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(16):
+            launch()
+        torch.cuda.synchronize()
+        done += 16
+    return done
+
+
+def _computed_delay_ms(frame, fir_len: int, reps: int, stream, x, out) -> dict:
+    """Envelope time of the same frame with plan-time delay tables (the default) and with the delays
+    of eq. (1) evaluated on the device from the geometry (DMAS_NO_DELAY_TABLE, read at plan creation)."""
+    from paper_2511_09165_amd import plan_for_frame
+    res = {}
+    for key, env in (("table", None), ("computed", "1")):
+        old = os.environ.pop("DMAS_NO_DELAY_TABLE", None)
+        if env:
+            os.environ["DMAS_NO_DELAY_TABLE"] = env
+        try:
+            with plan_for_frame(frame, fir_len=fir_len) as p:
+                info = p.info()
+                _timed(lambda: p.envelope(x, out=out), reps, 2, stream)   # clocks and caches
+                res[f"{key}_ms"] = _timed(lambda: p.envelope(x, out=out), reps, 2, stream)[1]
+                res[f"{key}_delay_table_bytes"] = info["delay_table_bytes"]
+        finally:
+            os.environ.pop("DMAS_NO_DELAY_TABLE", None)
+            if old is not None:
+                os.environ["DMAS_NO_DELAY_TABLE"] = old
+    res["computed_over_table"] = res["computed_ms"] / res["table_ms"]
+    return res
 
 
 def bench_headline(args) -> dict:
@@ -216,6 +275,7 @@ def bench_headline(args) -> dict:
     x = torch.from_numpy(frame.x_f32()).cuda()
     out = torch.empty((D, T), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
+    settle = _settle(lambda: plan.envelope(x, out=out), stream)
     ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), args.steps, args.warmup, stream)
     pixels = D * T
     workload_key = f"ertis32 M={M} D={D} T={T} n={n} cf=1 env L={fir_len}"
@@ -224,8 +284,10 @@ def bench_headline(args) -> dict:
                     "91x46 az/el directions, T=16384 samples at 450 kHz, 63-tap envelope FIR",
         "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len})
     rec["data"] = "synthetic (seeded eRTIS-like pulse-echo frame)"
-    rec["roofline"] = _roofline(launch_slots(M, T, D, n, True, fir_len), pixels, kernel_ms,
-                                measured_traffic(workload_key))
+    rec["clock_settle"] = {"launches": settle, "ms": 250,
+                           "note": "untimed launches before the warmup steps while the GPU clocks ramp up"}
+    rec["roofline"] = _roofline(launch_slots(M, T, D, n, True), pixels, kernel_ms,
+                                measured_traffic(workload_key), fir=fir_flops(D, T, fir_len))
     # per-launch statistics of the same call, then the RF image and CF off (the paper's Table III ratio)
     reps = max(5, args.steps // 2)
     rec["launch_stats"] = _launch_stats(lambda: plan.envelope(x, out=out), reps, stream)
@@ -233,13 +295,25 @@ def bench_headline(args) -> dict:
     with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
         extra["no_cf_env_ms"] = _timed(lambda: p2.envelope(x, out=out), reps, 2, stream)[1]
     extra["cf_cost"] = kernel_ms / extra["no_cf_env_ms"] - 1.0
+    if not args.no_delay_modes:
+        extra["delays_erti32"] = _computed_delay_ms(frame, fir_len, reps, stream, x, out)
+        near = synth.nearfield_frame()
+        xn = torch.from_numpy(near.x_f32()).cuda()
+        outn = torch.empty((near.num_dirs, near.num_samples), dtype=torch.float32, device="cuda")
+        extra["delays_nearfield1024"] = _computed_delay_ms(near, fir_len, 3, stream, xn, outn)
+        del xn, outn
+        torch.cuda.empty_cache()
     if args.extra:
         with plan_for_frame(frame, fir_len=fir_len, ng_fp64=True) as p3:
             extra["ng_fp64_env_ms"] = _timed(lambda: p3.envelope(x, out=out), reps, 2, stream)[1]
         extra["plan"] = plan.info()
     rec["extra"] = extra
-    rec["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(frame, fir_len)
     plan.close()
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        rec["serving"] = serving_summary(args)
+    rec["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(frame, fir_len)
     return rec
 
 
@@ -267,16 +341,16 @@ def bench_nearfield(args) -> dict:
         "fir_len": fir_len})
     rec["metric"] = "direction*samples/sec, order-3 DMAS+CF, 1024 mics, near field"
     rec["steps"] = steps
-    rec["roofline"] = _roofline(launch_slots(M, T, D, n, True, fir_len), pixels, kernel_ms)
+    rec["roofline"] = _roofline(launch_slots(M, T, D, n, True), pixels, kernel_ms, fir=fir_flops(D, T, fir_len))
     rec["extra"] = {"plan": info}
     return rec
 
 
-def linear_pixel_slots(M: int, n: int, cf: bool, fir_len: int) -> int:
+def linear_pixel_slots(M: int, n: int, cf: bool) -> int:
     """Slots per pixel with linear fractional delays: per microphone the interpolation (subtract,
     FMA) and the signed root of the interpolated value (a root of a channel sample cannot be
-    reused), then the same powers and sums, Newton-Girard, CF and envelope as ``pixel_slots``."""
-    return pixel_slots(M, n, cf, fir_len) + M * (2 + root_slots(n))
+    reused), then the same powers and sums, Newton-Girard, CF and scale as ``pixel_slots``."""
+    return pixel_slots(M, n, cf) + M * (2 + root_slots(n))
 
 
 def bench_linear(args) -> dict:
@@ -303,7 +377,8 @@ def bench_linear(args) -> dict:
         "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len, "delays": "linear"})
     rec["metric"] = "direction*samples/sec, order-5 DMAS+CF, 32 mics, linear fractional delays"
     rec["steps"] = steps
-    rec["roofline"] = _roofline(D * T * linear_pixel_slots(M, n, True, fir_len), pixels, kernel_ms)
+    rec["roofline"] = _roofline(D * T * linear_pixel_slots(M, n, True), pixels, kernel_ms,
+                                fir=fir_flops(D, T, fir_len))
     rec["extra"] = {"plan": info}
     return rec
 
@@ -337,8 +412,7 @@ def bench_pipeline(args) -> dict:
         env_ms = _timed(lambda: plan.envelope(x, out=out), steps, 2, stream)[1]
         info = plan.info()
     pixels = D * T
-    env_slots = (D * T * (pixel_slots(M, n, True, fir_len) - fir_len) + D * (-(-T // decim)) * fir_len
-                 + M * T * root_slots(n))
+    env_slots = D * T * pixel_slots(M, n, True) + M * T * root_slots(n)
     rec = _base_record(args, pixels / (ms_per_step * 1e-3), ms_per_step, "f32", {
         "workload": "raw eRTIS-like frame -> matched filter (450-sample 25-75 kHz chirp) -> order-5 DMAS+CF -> "
                     "63-tap envelope kept every 20th sample; M=32, 91x46 directions, T=16384 at 450 kHz",
@@ -346,7 +420,9 @@ def bench_pipeline(args) -> dict:
         "mf_len": P})
     rec["metric"] = "direction*samples/sec, raw -> matched filter -> order-5 DMAS+CF -> decimated envelope"
     rec["steps"] = steps
-    rec["roofline"] = _roofline(env_slots, pixels, env_ms)
+    # the FIR runs at full rate (every sample) on the matrix cores; the algorithmic count keeps
+    # only the stored outputs
+    rec["roofline"] = _roofline(env_slots, pixels, env_ms, fir=fir_flops(D, -(-T // decim), fir_len))
     mf_flops = 2.0 * M * T * P
     rec["matched_filter"] = {"kernel_ms": mf_ms, "bound": "mfma", "achieved": mf_flops / (mf_ms * 1e-3) / 1e12,
                              "peak": MFMA_F32_FLOPS / 1e12, "unit": "TFLOP/s",
@@ -394,6 +470,113 @@ def bench_precision(args) -> list:
     return recs
 
 
+SERVING_MODES = {"batched": dict(num_streams=2, max_batch=64),
+                 "one_launch_per_frame": dict(num_streams=1, max_batch=1),
+                 "resident": dict(num_streams=2, max_batch=64, resident=True)}
+
+
+def _serve_trace(mode: str, plans, xs, pix, arrivals_gaps, picks, rate: float) -> dict:
+    """One server of ``mode`` fed the Poisson trace (gaps between arrivals, pool index per frame).
+    Latency = completion - scheduled arrival; throughput and latency count completed frames only,
+    failed frames are counted apart."""
+    from paper_2511_09165_amd import DmasError, Server, server_clock
+
+    n_frames = len(picks)
+    with Server(hbm_budget=64 << 30, staging=2 << 30, **SERVING_MODES[mode]) as srv:
+        # warm up every kernel the trace can use: each plan alone, then all at once
+        for k in range(len(plans)):
+            srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
+            srv.drain(600)
+        for k in range(len(plans)):
+            srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
+        srv.drain(600)
+        srv.completed(100000)
+        st0 = srv.stats()
+        launches0 = st0["launches"]
+        t0 = server_clock() + 0.05
+        arrivals = t0 + np.cumsum(arrivals_gaps)
+        busy_retries = 0
+        late = []
+        gc.collect()
+        gc.disable()   # keep collector pauses of the load generator out of the latencies
+        try:
+            for a, k in zip(arrivals, picks):
+                while server_clock() < a:
+                    pass
+                late.append(server_clock() - a)
+                while True:
+                    try:
+                        srv.submit(plans[k], xs[k], envelope=True, auto_release=True, arrival=float(a))
+                        break
+                    except DmasError as e:
+                        if e.status != 5:
+                            raise
+                        busy_retries += 1
+        finally:
+            gc.enable()
+        srv.drain(600)
+        recs = srv.completed(n_frames + 10)
+        st = srv.stats()
+    ok = [r for r in recs if r["state"] == 3]
+    failed = max(st["failed"] - st0["failed"], len(recs) - len(ok))
+    lat = np.array([r["t_done"] - r["t_arrival"] for r in ok]) * 1e3
+    slow = sorted(ok, key=lambda r: r["t_done"] - r["t_arrival"])[-3:]
+    slowest = [{"ms": round((r["t_done"] - r["t_arrival"]) * 1e3, 2),
+                "queued_ms": round((r["t_admit"] - r["t_arrival"]) * 1e3, 2),
+                "wait_launch_ms": round((r["t_launch"] - r["t_admit"]) * 1e3, 2),
+                "run_ms": round((r["t_done"] - r["t_launch"]) * 1e3, 2),
+                "frames_in_launch": r["batch_frames"], "pixels": r["pixels"]} for r in slow]
+    done = np.array([r["t_done"] for r in ok])
+    ok_pix = float(sum(r["pixels"] for r in ok))
+    span = float(done.max() - arrivals[0]) if ok else float("nan")
+    return {"workload": "serving", "mode": mode, "offered_frames_per_s": rate, "offered_frames": n_frames,
+            "frames": len(ok), "failed": int(failed),
+            "achieved_frames_per_s": len(ok) / span, "direction_samples_per_s": ok_pix / span,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "launches": st["launches"] - launches0,
+            "mean_frames_per_launch": len(ok) / max(1, st["launches"] - launches0),
+            "resident_launches": st["resident_launches"] - st0["resident_launches"],
+            "resident_frames": st["resident_frames"] - st0["resident_frames"],
+            "hbm_peak_gb": st["hbm_peak"] / 1e9, "busy_retries": busy_retries,
+            "client_late_max_ms": float(max(late)) * 1e3, "slowest": slowest}
+
+
+def _serving_pool(args, orders=(3, 5)):
+    import synth
+    from paper_2511_09165_amd import plan_for_frame
+    pool = synth.serving_pool(n_arrays_per_m=4, max_frames=args.serving_pool, orders=orders)
+    plans = [plan_for_frame(f) for f in pool]
+    return pool, plans, [f.x_f32() for f in pool], [f.num_dirs * f.num_samples for f in pool]
+
+
+def serving_summary(args) -> dict:
+    """The serving leg of the headline line: the mixed-frame pool (16/32/64 microphones, 1024-8192
+    directions, orders 3 and 5, 4096-16384 samples) under Poisson arrivals at 2000 frames/s for
+    ``--serving-summary-s`` seconds, through the batched server and through one plain launch per
+    frame on the same trace."""
+    pool, plans, xs, pix = _serving_pool(args)
+    rate = 2000.0
+    rng = np.random.default_rng(2511091654)
+    n_frames = max(20, int(rate * args.serving_summary_s))
+    gaps = rng.exponential(1.0 / rate, size=n_frames)
+    picks = rng.integers(0, len(pool), size=n_frames)
+    res = {"workload": f"{len(pool)} distinct frames (M in 16/32/64, D 1024-8192, n in 3/5, T 4096-16384, "
+                       f"CF, envelope), Poisson arrivals", "offered_frames_per_s": rate,
+           "duration_s": args.serving_summary_s, "frames": n_frames, "hbm_budget_gb": 64 * 2**30 / 1e9}
+    try:
+        for mode in ("batched", "one_launch_per_frame"):
+            r = _serve_trace(mode, plans, xs, pix, gaps, picks, rate)
+            res[mode] = {k: r[k] for k in ("p50_ms", "p99_ms", "max_ms", "achieved_frames_per_s",
+                                           "direction_samples_per_s", "frames", "failed", "launches",
+                                           "mean_frames_per_launch")}
+    finally:
+        for p in plans:
+            p.close()
+    res["p50_ms"] = res["batched"]["p50_ms"]
+    res["p99_ms"] = res["batched"]["p99_ms"]
+    return res
+
+
 def bench_serving(args) -> list:
     """Serving: Poisson arrivals of heterogeneous pulse-echo frames; batched server, one launch per frame,
     and resident workers (persistent launches fed by a job queue).
@@ -403,82 +586,22 @@ def bench_serving(args) -> list:
     output kept on the device (released at completion). Each rate point
     offers ``rate * duration`` frames; latency = completion - scheduled arrival.
     """
-    import synth
-    from paper_2511_09165_amd import DmasError, Server, plan_for_frame, server_clock
-
     orders = tuple(int(n) for n in args.serving_orders.split(","))
-    pool = synth.serving_pool(n_arrays_per_m=4, max_frames=args.serving_pool, orders=orders)
-    plans = [plan_for_frame(f) for f in pool]
-    xs = [f.x_f32() for f in pool]
-    pix = [f.num_dirs * f.num_samples for f in pool]
+    pool, plans, xs, pix = _serving_pool(args, orders)
     rng = np.random.default_rng(2511091654)
     rates = [float(r) for r in args.serving_rates.split(",")]
     out = []
-    all_modes = {"batched": dict(num_streams=2, max_batch=64),
-                 "one_launch_per_frame": dict(num_streams=1, max_batch=1),
-                 "resident": dict(num_streams=2, max_batch=64, resident=True)}
-    modes = [(m, all_modes[m]) for m in args.serving_modes.split(",")]
-    for rate in rates:
-        n_frames = max(20, int(rate * args.serving_duration))
-        gaps = rng.exponential(1.0 / rate, size=n_frames)
-        picks = rng.integers(0, len(pool), size=n_frames)
-        for mode, kw in modes:
-            with Server(hbm_budget=64 << 30, staging=2 << 30, **kw) as srv:
-                # warm up every kernel the trace can use: each plan alone, then all at once
-                for k in range(len(pool)):
-                    srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
-                    srv.drain(600)
-                for k in range(len(pool)):
-                    srv.submit(plans[k], xs[k], envelope=True, auto_release=True)
-                srv.drain(600)
-                srv.completed(100000)
-                st0 = srv.stats()
-                launches0 = st0["launches"]
-                t0 = server_clock() + 0.05
-                arrivals = t0 + np.cumsum(gaps)
-                busy_retries = 0
-                late = []
-                gc.collect()
-                gc.disable()   # keep collector pauses of the load generator out of the latencies
-                for a, k in zip(arrivals, picks):
-                    while server_clock() < a:
-                        pass
-                    late.append(server_clock() - a)
-                    while True:
-                        try:
-                            srv.submit(plans[k], xs[k], envelope=True, auto_release=True, arrival=float(a))
-                            break
-                        except DmasError as e:
-                            if e.status != 5:
-                                raise
-                            busy_retries += 1
-                gc.enable()
-                srv.drain(600)
-                recs = srv.completed(n_frames + 10)
-                st = srv.stats()
-            lat = np.array([r["t_done"] - r["t_arrival"] for r in recs]) * 1e3
-            slow = sorted(recs, key=lambda r: r["t_done"] - r["t_arrival"])[-3:]
-            slowest = [{"ms": round((r["t_done"] - r["t_arrival"]) * 1e3, 2),
-                        "queued_ms": round((r["t_admit"] - r["t_arrival"]) * 1e3, 2),
-                        "wait_launch_ms": round((r["t_launch"] - r["t_admit"]) * 1e3, 2),
-                        "run_ms": round((r["t_done"] - r["t_launch"]) * 1e3, 2),
-                        "frames_in_launch": r["batch_frames"], "pixels": r["pixels"]} for r in slow]
-            done = np.array([r["t_done"] for r in recs])
-            total_pix = float(sum(pix[k] for k in picks))
-            span = float(done.max() - arrivals[0])
-            out.append({"workload": "serving", "mode": mode, "offered_frames_per_s": rate, "frames": len(recs),
-                        "achieved_frames_per_s": len(recs) / span,
-                        "direction_samples_per_s": total_pix / span,
-                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                        "max_ms": float(lat.max()), "launches": st["launches"] - launches0,
-                        "mean_frames_per_launch": len(recs) / max(1, st["launches"] - launches0),
-                        "resident_launches": st["resident_launches"] - st0["resident_launches"],
-                        "resident_frames": st["resident_frames"] - st0["resident_frames"],
-                        "hbm_peak_gb": st["hbm_peak"] / 1e9, "busy_retries": busy_retries,
-                        "client_late_max_ms": float(max(late)) * 1e3, "slowest": slowest})
-            print(json.dumps(out[-1]), flush=True)
-    for p in plans:
-        p.close()
+    try:
+        for rate in rates:
+            n_frames = max(20, int(rate * args.serving_duration))
+            gaps = rng.exponential(1.0 / rate, size=n_frames)
+            picks = rng.integers(0, len(pool), size=n_frames)
+            for mode in args.serving_modes.split(","):
+                out.append(_serve_trace(mode, plans, xs, pix, gaps, picks, rate))
+                print(json.dumps(out[-1]), flush=True)
+    finally:
+        for p in plans:
+            p.close()
     return out
 
 
@@ -500,6 +623,11 @@ def main(argv=None) -> int:
                          "linear: the headline frame with linear fractional delays; pipeline: raw channels "
                          "-> matched filter -> DMAS+CF -> decimated envelope")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="headline line without its serving leg")
+    ap.add_argument("--serving-summary-s", type=float, default=1.0,
+                    help="seconds of 2000 frames/s arrivals in the headline line's serving leg")
+    ap.add_argument("--no-delay-modes", action="store_true",
+                    help="headline line without the computed-delay timings (plan tables vs eq. (1) on the device)")
     ap.add_argument("--extra", action="store_true", help="also time FP64 Newton-Girard and print the plan")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, --steps times (HBM counter calibration)")

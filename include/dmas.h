@@ -26,8 +26,10 @@
  *     NEAREST mode uses floor(fs*tau + 1/2) whole samples; the LINEAR mode
  *     interpolates between floor(fs*tau) and floor(fs*tau) + 1.
  *     Samples outside [0, T) are zero.
- *   - Signed root: sgn(0) = 0. Channel values below the FP32 normal range
- *     (|x| < 2^-126) enter the root as zero.
+ *   - Signed root: sgn(0) = 0. With whole-sample delays every finite channel
+ *     value, including values below the FP32 normal range (|x| < 2^-126),
+ *     gets its root per eq. (4). With LINEAR delays an interpolated value
+ *     below the normal range enters the root as zero.
  *   - Coherence factor: CF = (sum x_i)^2 / (M * sum x_i^2 + cf_eps) on the
  *     delayed samples; y = E_n * CF.
  *   - Envelope: env[t] = sum_k h[k] * |y[t + (L-1)/2 - k]|, y = 0 outside

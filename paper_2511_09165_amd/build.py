@@ -61,12 +61,6 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    probe = os.path.join(HERE, "valu_probe")
-    cmd = [_hipcc(), *COMMON, os.path.join(CSRC, "valu_probe.hip"), "-o", probe + ".tmp"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{r.stdout}\n{r.stderr}")
-    os.replace(probe + ".tmp", probe)
     return LIB
 
 

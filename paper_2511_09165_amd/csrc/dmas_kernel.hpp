@@ -162,13 +162,26 @@ __device__ __forceinline__ void stage_row(float *__restrict__ dst, const void *_
 
 // Signed n-th root of one sample, eq. (4): sgn(x) |x|^(1/n) in FP32.
 // |x|^(1/n) = 2^(log2|x| / n); log2(0) = -inf gives 0.
-template <int N>
+// The hardware log2 and square root take an input below the FP32 normal range
+// (|x| < 2^-126) as zero. With SUBNORMAL such an input is first scaled by
+// 2^32 (exact) and the scale is taken back out of the result, so the root
+// follows eq. (4) for every finite input; normal inputs give the same bits
+// either way. The root pass (once per channel sample) uses it; the linear-delay
+// kernels, which take a root per microphone and pixel, do not.
+template <int N, bool SUBNORMAL = false>
 __device__ __forceinline__ float signed_root(float xv)
 {
     const float ax = __builtin_fabsf(xv);
     float r;
-    if constexpr (N == 2) r = __builtin_amdgcn_sqrtf(ax);
-    else r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(ax) * (1.0f / (float)N));
+    if constexpr (SUBNORMAL) {
+        const bool tiny = ax < 0x1p-126f;
+        const float as = tiny ? ax * 0x1p+32f : ax;
+        if constexpr (N == 2) r = __builtin_amdgcn_sqrtf(as) * (tiny ? 0x1p-16f : 1.0f);
+        else r = __builtin_amdgcn_exp2f((__builtin_amdgcn_logf(as) - (tiny ? 32.0f : 0.0f)) * (1.0f / (float)N));
+    } else {
+        if constexpr (N == 2) r = __builtin_amdgcn_sqrtf(ax);
+        else r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(ax) * (1.0f / (float)N));
+    }
     return __builtin_copysignf(r, xv);
 }
 
@@ -186,7 +199,7 @@ __global__ void __launch_bounds__(256) root_plane_kernel(const void *__restrict_
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
         const float v = load_sample<DT>(x, e);
-        plane[e] = make_float2(signed_root<N>(v), v);
+        plane[e] = make_float2(signed_root<N, true>(v), v);
     }
 }
 

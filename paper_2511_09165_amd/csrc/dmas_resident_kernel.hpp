@@ -87,7 +87,7 @@ __device__ __forceinline__ void roots_item(const ResidentJob &jd, int item)
 #pragma unroll
     for (int k = 0; k < kRootLoads; ++k) {
         const int64_t e = e0 + (int64_t)k * (kDirsPerTile * kWaveSize);
-        if (e < jd.count) plane[e] = make_float2(signed_root<N>(v[k]), v[k]);
+        if (e < jd.count) plane[e] = make_float2(signed_root<N, true>(v[k]), v[k]);
     }
 }
 

@@ -56,7 +56,7 @@ def _compare(frame, x32, rows=None, check_env=True, taps=None, t2=True, interp=F
         res["env_t1"] = check_t1(env, env_ref)
         if t2:
             res["env_t2"] = check_t2(env, env_ref, env_bound(tol, np.abs(y_ref), taps32, oracle.envelope))
-        res["env_db"] = check_t3(env, env_ref, tol_db=0.05)
+        res["env_db"] = check_t3(env, env_ref)
     return res
 
 
@@ -294,6 +294,119 @@ def test_determinism_and_streams():
             b = plan.envelope(x, stream=s2)
         torch.cuda.synchronize()
         assert np.array_equal(a.cpu().numpy(), ref) and np.array_equal(b.cpu().numpy(), ref)
+
+
+def _shifted(x, k):
+    """Every channel delayed by k samples: xs[:, t] = x[:, t - k], zero before sample k."""
+    xs = np.zeros_like(x)
+    xs[:, k:] = x[:, :x.shape[1] - k]
+    return xs
+
+
+@pytest.mark.parametrize("k", [1, 37, 64, 1000])
+@pytest.mark.parametrize("nearfield", [False, True])
+def test_time_shift_bitwise(k, nearfield):
+    """Shifting every channel by k samples shifts the RF image by k bit for bit, wherever neither
+    image reads a delayed sample outside the record (eq. (1): pixel (t, p) reads m_i(t + d_ip) only)."""
+    f = synth.random_frame(np.random.default_rng(70 + k), 20, 30, 2100, 5, nearfield=nearfield)
+    _say(f"time shift k={k} near={nearfield}")
+    x = f.x_f32()
+    y = _run(f, x)
+    ys = _run(f, _shifted(x, k))
+    d = oracle.delays(f.mic_pos, f.dirs, f.fs, f.c, f.nearfield)
+    lo, hi = k - int(d.min()), f.num_samples - int(d.max())
+    assert hi - lo > 1000
+    np.testing.assert_array_equal(ys[:, lo:hi], y[:, lo - k:hi - k])
+
+
+@pytest.mark.parametrize("k", [256, 768])
+def test_time_shift_envelope_bitwise(k, monkeypatch):
+    """With one time segment per tile the envelope FIR groups its products by the output's position
+    within a 256-sample chunk, so a shift by a multiple of 256 moves the envelope bit for bit in the
+    interior (where the FIR window of both images stays inside the shift-covariant RF interior)."""
+    monkeypatch.setenv("DMAS_SEGMENT", "4096")
+    f = synth.random_frame(np.random.default_rng(80 + k), 20, 30, 3000, 3)
+    _say(f"envelope time shift k={k}")
+    x = f.x_f32()
+    e = _run(f, x, env=True)
+    es = _run(f, _shifted(x, k), env=True)
+    d = oracle.delays(f.mic_pos, f.dirs, f.fs, f.c, f.nearfield)
+    H = 31
+    lo, hi = k - int(d.min()) + H, f.num_samples - int(d.max()) - H
+    assert hi - lo > 1000
+    np.testing.assert_array_equal(es[:, lo:hi], e[:, lo - k:hi - k])
+    check_t1(es, oracle.envelope(oracle.frame_rows(f, x=_shifted(x, k).astype(np.float64)),
+                                 oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32).astype(np.float64)))
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+@pytest.mark.parametrize("use_cf", [False, True])
+def test_n_minus_one_channels_cancel(n, use_cf):
+    """Exactly n - 1 non-zero channels: E_n has no term without a zero root (eq. (5)), so the exact
+    image is 0; the Newton-Girard evaluation leaves only rounding, within the per-pixel bound T2."""
+    rng = np.random.default_rng(90 + n)
+    f = synth.random_frame(rng, 16, 24, 900, n, use_cf=use_cf)
+    keep = rng.choice(16, size=n - 1, replace=False)
+    mask = np.zeros((16, 1))
+    mask[keep] = 1.0
+    f.x = f.x * mask
+    x32 = f.x_f32()
+    x64 = x32.astype(np.float64)
+    _say(f"n-1 channels n={n} cf={use_cf}")
+    y_ref, dg = oracle.frame_rows(f, x=x64, diag=True)
+    assert np.all(y_ref == 0.0)
+    y = _run(f, x32)
+    tol = y_bound(dg, 16, n, use_cf, root_rel_error(x64))
+    worst = check_t2(y, y_ref, tol)
+    env = _run(f, x32, env=True)
+    taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32)
+    check_t2(env, np.zeros_like(env), env_bound(tol, np.abs(y_ref), taps, oracle.envelope))
+    _say(f"n-1 channels n={n} cf={use_cf}: worst |y| at {worst:.3g} of its bound, max |y| {np.abs(y).max():.3g}")
+
+
+def _with_subnormals(rng, x, frac=0.3):
+    """FP32 channels with a fraction of the samples replaced by values below the normal range,
+    each channel's replaced samples at one random exponent in [-149, -127]."""
+    x = x.astype(np.float32).copy()
+    for i in range(x.shape[0]):
+        pick = rng.random(x.shape[1]) < frac
+        mag = np.float32(2.0 ** rng.integers(-149, -126)) * rng.uniform(1.0, 2.0, pick.sum()).astype(np.float32)
+        x[i, pick] = np.copysign(mag, rng.standard_normal(pick.sum())).astype(np.float32)
+    assert np.any((x != 0) & (np.abs(x) < np.float32(2.0 ** -126)))
+    return x
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_subnormal_samples(n):
+    """Channels mixing normal and subnormal samples, and channels of subnormal samples only: the root
+    pass takes every finite sample's root per eq. (4), so the image matches the oracle on the same
+    FP32 values within T1 and T2 (with the root error bound at the smallest exponent present)."""
+    rng = np.random.default_rng(110 + n)
+    f = synth.random_frame(rng, 12, 21, 700, n)
+    x32 = _with_subnormals(rng, f.x_f32())
+    x32[:3] = _with_subnormals(rng, np.zeros((3, 700)), frac=1.0)   # three channels below the normal range only
+    _say(f"subnormal samples n={n}")
+    res = _compare(f, x32)
+    _say(f"subnormal samples n={n}: {res}")
+    # a frame of subnormal samples only (no CF, so the image is not squared away): still eq. (4)
+    f.use_cf = False
+    tiny = _with_subnormals(rng, np.zeros((12, 700)), frac=1.0)
+    y_ref = oracle.frame_rows(f, x=tiny.astype(np.float64))
+    assert np.abs(y_ref).max() > 0
+    res = _compare(f, tiny, check_env=False)
+    _say(f"subnormal-only frame n={n}: {res}")
+
+
+def test_subnormal_samples_linear_delays():
+    """Linear delays take a root per microphone and pixel without the subnormal step: an interpolated
+    value below 2^-126 enters the root as 0. On a frame mixing normal and subnormal samples that stays
+    within T1 of the oracle."""
+    rng = np.random.default_rng(120)
+    f = synth.random_frame(rng, 12, 21, 700, 3)
+    x32 = _with_subnormals(rng, f.x_f32())
+    _say("subnormal samples, linear delays")
+    res = _compare(f, x32, interp=True, t2=False)
+    _say(f"subnormal samples linear: {res}")
 
 
 # ---------------------------------------------------------------------------
