@@ -186,6 +186,28 @@ dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y,
 dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env,
                             float in_scale, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): dmas_envelope
+ * with the root plane taken from a fixed array of DMAS_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device until the process ends, instead of
+ * the stream-ordered pool. The call allocates nothing (no hipMalloc, hipFree
+ * or pool allocation); it computes the same kernels and gives the same bits
+ * as dmas_envelope. Arguments as for dmas_envelope.
+ * Limit: a plan whose root plane (M * T * 8 bytes; whole-sample delays and
+ * n >= 2) exceeds DMAS_NOALLOC_SCRATCH_BYTES returns DMAS_ERR_UNSUPPORTED
+ * and launches nothing; plans without a root plane (n = 1, LINEAR delays)
+ * use no scratch.
+ * Sharing: every call on a device uses that device's one array. Calls whose
+ * work overlaps in time on one device (several streams or host threads
+ * without ordering between them) race on it and give wrong results; calls
+ * queued one after another on one stream are safe. The array keeps the last
+ * call's roots; each call writes every element it later reads, so nothing
+ * in it needs to start at zero.
+ * Errors as for dmas_envelope, except that there is no allocation to fail. */
+#define DMAS_NOALLOC_SCRATCH_BYTES (16u << 20)
+dmas_status_t dmas_envelope_noalloc(dmas_plan_t plan, const void *d_x, float *d_env,
+                                    float in_scale, void *stream);
+
 /* Matched filter (pulse compression, the pipeline step before the
  * beamformer, Section II): d_x[i*T + t] = sum_{k < mf_len} d_raw[i*T + t + k]
  * * pulse[k], raw = 0 beyond the record. d_raw and d_x are M x T FP32 device

@@ -408,8 +408,43 @@ hipError_t device_pool(int dev, hipMemPool_t *out)
     return hipSuccess;
 }
 
+// Root plane of dmas_envelope_noalloc: one array per device for the
+// library's lifetime, so that entry point allocates nothing. Host code uses
+// the device address that hipGetSymbolAddress returns for the current device
+// (the array's name on the host is only a stand-in for the symbol).
+static __device__ __align__(256) float2 scratch[DMAS_NOALLOC_SCRATCH_BYTES / sizeof(float2)];
+
+std::mutex g_scratch_mutex;
+std::vector<float2 *> g_scratch;   // per device: address of `scratch`, null until looked up
+
+// Address of `scratch` on device dev, which must be current: looked up on the
+// first call for that device and kept.
+hipError_t scratch_address(int dev, float2 **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch.empty()) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess) return e;
+        g_scratch.assign((size_t)std::max(n, 1), nullptr);
+    }
+    if (dev < 0 || dev >= (int)g_scratch.size()) return hipErrorInvalidDevice;
+    if (!g_scratch[dev]) {
+        float2 *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+// One beamforming launch. The root plane comes from the per-device pool
+// (stream-ordered allocation around the launch), or with noalloc from the
+// per-device `scratch` array.
 dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scale, void *stream,
-                  bool env)
+                  bool env, bool noalloc = false)
 {
     if (!plan) return fail(DMAS_ERR_INVALID_ARG, "plan is NULL");
     if (!d_x || !d_out) return fail(DMAS_ERR_INVALID_ARG, "device pointer is NULL");
@@ -422,6 +457,27 @@ dmas_status_t run(dmas_plan_t plan, const void *d_x, float *d_out, float in_scal
     hipStream_t st = static_cast<hipStream_t>(stream);
     float2 *plane = nullptr;
     hipError_t e = hipSuccess;
+    if (plan->roots && noalloc) {
+        const size_t need = dmas::plane_bytes(plan);
+        if (need > DMAS_NOALLOC_SCRATCH_BYTES)
+            return fail(DMAS_ERR_UNSUPPORTED,
+                        "root plane of %zu bytes (M=%d x T=%d x 8) exceeds the %zu-byte fixed scratch of "
+                        "dmas_envelope_noalloc",
+                        need, plan->M, plan->T, (size_t)DMAS_NOALLOC_SCRATCH_BYTES);
+        float2 *fixed = nullptr;
+        e = scratch_address(plan->device, &fixed);
+        if (e != hipSuccess) return hip_fail(e, "address of the fixed root-plane scratch");
+        // every element the kernel reads is written here first: nothing needs clearing
+        e = dmas::stage_roots(plan, d_x, fixed, st);
+        if (e != hipSuccess) return hip_fail(e, "root-plane launch");
+        const dmas::KernelParams kp = dmas::make_params(plan, d_x, fixed, d_out, in_scale, env);
+        e = dmas::launch_plan(plan->order, &kp, dmas::shape_of(plan, env), st);
+        if (e == hipErrorNotSupported)
+            return fail(DMAS_ERR_UNSUPPORTED, "no kernel for order %d cf=%d env=%d near=%d accumulate=%d",
+                        plan->order, (int)plan->cf, (int)env, (int)plan->nearfield, (int)plan->compensated);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return DMAS_OK;
+    }
     if (plan->roots) {
         hipMemPool_t pool = nullptr;
         e = device_pool(plan->device, &pool);
@@ -807,6 +863,12 @@ dmas_status_t dmas_beamform(dmas_plan_t plan, const void *d_x, float *d_y, float
 dmas_status_t dmas_envelope(dmas_plan_t plan, const void *d_x, float *d_env, float in_scale, void *stream)
 {
     return run(plan, d_x, d_env, in_scale, stream, true);
+}
+
+dmas_status_t dmas_envelope_noalloc(dmas_plan_t plan, const void *d_x, float *d_env, float in_scale,
+                                    void *stream)
+{
+    return run(plan, d_x, d_env, in_scale, stream, true, true);
 }
 
 dmas_status_t dmas_matched_filter(dmas_plan_t p, const float *d_raw, float *d_x, void *stream)

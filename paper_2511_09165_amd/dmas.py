@@ -24,8 +24,8 @@ SUBMIT_AUTO_RELEASE = 2
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 ACCUMULATE = {"f32": 0, "kahan": 1, "f64": 2}   # dmas_accumulate_t
 EXPORTED = ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
-            "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass",
-            "dmas_matched_filter", "dmas_last_error", "dmas_version",
+            "dmas_beamform", "dmas_envelope", "dmas_envelope_noalloc", "dmas_steering_delays",
+            "dmas_design_lowpass", "dmas_matched_filter", "dmas_last_error", "dmas_version",
             "dmas_server_clock", "dmas_server_create", "dmas_server_submit", "dmas_server_query",
             "dmas_server_wait", "dmas_server_release", "dmas_server_fetch", "dmas_server_completed",
             "dmas_server_drain", "dmas_server_stats", "dmas_server_destroy")
@@ -98,13 +98,15 @@ def load_library(path: Optional[str] = None):
     lib.dmas_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.dmas_beamform.argtypes = [vp, vp, vp, ctypes.c_float, vp]
     lib.dmas_envelope.argtypes = [vp, vp, vp, ctypes.c_float, vp]
+    lib.dmas_envelope_noalloc.argtypes = [vp, vp, vp, ctypes.c_float, vp]
     lib.dmas_steering_delays.argtypes = [vp, vp, vp, vp]
     lib.dmas_matched_filter.argtypes = [vp, vp, vp, vp]
     lib.dmas_matched_filter.restype = st
     lib.dmas_design_lowpass.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_float)]
     for name in ("dmas_plan_desc_init", "dmas_plan_create", "dmas_plan_destroy", "dmas_plan_query",
-                 "dmas_beamform", "dmas_envelope", "dmas_steering_delays", "dmas_design_lowpass"):
+                 "dmas_beamform", "dmas_envelope", "dmas_envelope_noalloc", "dmas_steering_delays",
+                 "dmas_design_lowpass"):
         getattr(lib, name).restype = st
     lib.dmas_server_clock.restype = ctypes.c_double
     lib.dmas_server_create.argtypes = [ctypes.POINTER(ServerDesc), ctypes.POINTER(vp)]
@@ -278,6 +280,17 @@ class Plan:
         _check(self._lib.dmas_envelope(self._handle, ctypes.c_void_p(x.data_ptr()),
                                        ctypes.c_void_p(out.data_ptr()), float(in_scale),
                                        ctypes.c_void_p(_stream_handle(stream))))
+        return out
+
+    def envelope_noalloc(self, x, out, in_scale: float = 1.0, stream=None):
+        """``envelope`` through dmas_envelope_noalloc: the root plane lives in the library's fixed
+        per-device scratch, so the call allocates nothing; ``out`` must be given. Calls that
+        overlap on one device race on that scratch."""
+        self._check_input(x)
+        out = self._out(x, out, self.env_samples)
+        _check(self._lib.dmas_envelope_noalloc(self._handle, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), float(in_scale),
+                                               ctypes.c_void_p(_stream_handle(stream))))
         return out
 
     def matched_filter(self, raw, out=None, stream=None):

@@ -142,6 +142,7 @@ def test_null_arguments(lib):
     assert lib.dmas_plan_destroy(None) == 0
     assert lib.dmas_beamform(None, None, None, ctypes.c_float(1.0), None) == 1
     assert lib.dmas_envelope(None, None, None, ctypes.c_float(1.0), None) == 1
+    assert lib.dmas_envelope_noalloc(None, None, None, ctypes.c_float(1.0), None) == 1
     assert lib.dmas_steering_delays(None, None, None, None) == 1
     assert lib.dmas_plan_query(None, None) == 1
     d, keep = _desc(lib)
