@@ -333,53 +333,77 @@ __device__ __forceinline__ void accumulate_root(Acc<N, CF, ACC> &acc, float sv, 
     if constexpr (CF) acc_fma<ACC>(acc.b, acc.cb, x, x);
 }
 
+// The first microphone of a chunk (plain FP32 sums): the same operations
+// applied to sums that are zero (literal zeros, so the sums need no clearing
+// between chunks and the bits equal those of clearing first); P_2 takes s*s,
+// which equals fma(s, s, +0). Compensated and FP64 sums are cleared after
+// each epilogue instead (their kernels run at a register cap, and the peeled
+// first microphone raised their spills).
 template <int N, bool CF, int ACC>
+__device__ __forceinline__ void accumulate_root_first(Acc<N, CF, ACC> &acc, float sv, float xv)
+{
+    static_assert(ACC == kAccF32, "only plain sums start from the first microphone");
+    Acc<N, CF, ACC> z;
+    z.zero();
+    accumulate_root<N, CF, ACC>(z, sv, xv);
+    if constexpr (N >= 3) z.p[2] = sv * sv;
+    acc = z;
+}
+
+template <int N, bool CF, int ACC, bool FIRST = false>
 __device__ __forceinline__ void accumulate(Acc<N, CF, ACC> &acc, float xv)
 {
-    accumulate_root<N, CF, ACC>(acc, N == 1 ? xv : signed_root<N>(xv), xv);
+    const float sv = N == 1 ? xv : signed_root<N>(xv);
+    if constexpr (FIRST) accumulate_root_first<N, CF, ACC>(acc, sv, xv);
+    else accumulate_root<N, CF, ACC>(acc, sv, xv);
 }
 
 // ---------------------------------------------------------------------------
 // Newton-Girard: E_n from P_1..P_n. Orders 2..5 use the paper's expansions,
-// eqs. (9)-(12); higher orders use the recursive form of the same identities
-// (k e_k = sum_{i=1..k} (-1)^(i-1) e_{k-i} P_i), equivalent to eq. (8).
+// eqs. (9)-(12), multiplied by n! and nested in P_1 (Horner form: the same
+// polynomial, with fewer operations); higher orders use the recursive form of
+// the same identities (k e_k = sum_{i=1..k} (-1)^(i-1) e_{k-i} P_i),
+// equivalent to eq. (8).
 // ---------------------------------------------------------------------------
-// The expansions are written as explicit fused multiply-adds (and rounded
-// products), so the rounding does not depend on the compiler's contraction
-// choices in the surrounding kernel.
+// newton_girard_scaled returns F with E_n = F * ng_scale(N): n! E_n for
+// n <= 5 (so 1/n! can be folded into the output scale), E_n itself above.
+// Written as explicit fused multiply-adds (and rounded products), so the
+// rounding does not depend on the compiler's contraction choices in the
+// surrounding kernel.
+__host__ __device__ constexpr double ng_scale(int n)
+{
+    return n == 2 ? 1.0 / 2.0 : n == 3 ? 1.0 / 6.0 : n == 4 ? 1.0 / 24.0 : n == 5 ? 1.0 / 120.0 : 1.0;
+}
+
 template <int N, typename R>
-__device__ __forceinline__ R newton_girard(const R *P)
+__device__ __forceinline__ R newton_girard_scaled(const R *P)
 {
     if constexpr (N == 1) {
         return P[1];
     } else if constexpr (N == 2) {
-        // (P1^2 - P2) / 2
-        return R(0.5) * fma_t(P[1], P[1], -P[2]);
+        // P1^2 - P2
+        return fma_t(P[1], P[1], -P[2]);
     } else if constexpr (N == 3) {
-        // (P1^3 - 3 P1 P2 + 2 P3) / 6
-        const R q = mul_rounded(P[1], P[1]);
-        R t = fma_t(q, P[1], R(2) * P[3]);
-        t = fma_t(mul_rounded(R(-3), P[1]), P[2], t);
-        return R(1.0 / 6.0) * t;
+        // P1^3 - 3 P1 P2 + 2 P3 = P1 (P1^2 - 3 P2) + 2 P3
+        const R a = fma_t(P[1], P[1], mul_rounded(R(-3), P[2]));
+        return fma_t(P[1], a, R(2) * P[3]);
     } else if constexpr (N == 4) {
-        // (P1^4 - 6 P1^2 P2 + 3 P2^2 + 8 P1 P3 - 6 P4) / 24
-        const R q = mul_rounded(P[1], P[1]);
-        R t = fma_t(q, q, R(-6) * P[4]);
-        t = fma_t(mul_rounded(R(3), P[2]), P[2], t);
-        t = fma_t(mul_rounded(R(-6), P[2]), q, t);
-        t = fma_t(mul_rounded(R(8), P[3]), P[1], t);
-        return R(1.0 / 24.0) * t;
+        // P1^4 - 6 P1^2 P2 + 3 P2^2 + 8 P1 P3 - 6 P4
+        //   = P1 (P1 (P1^2 - 6 P2) + 8 P3) + (3 P2^2 - 6 P4)
+        const R a = fma_t(P[1], P[1], mul_rounded(R(-6), P[2]));
+        const R b = fma_t(P[1], a, R(8) * P[3]);
+        const R c = fma_t(mul_rounded(R(3), P[2]), P[2], mul_rounded(R(-6), P[4]));
+        return fma_t(P[1], b, c);
     } else if constexpr (N == 5) {
-        // (P1^5 - 10 P1^3 P2 + 15 P1 P2^2 + 20 P1^2 P3 - 20 P2 P3 - 30 P1 P4 + 24 P5) / 120
-        const R q = mul_rounded(P[1], P[1]);
-        const R c = mul_rounded(q, P[1]);
-        R t = fma_t(mul_rounded(q, q), P[1], R(24) * P[5]);
-        t = fma_t(mul_rounded(R(-10), P[2]), c, t);
-        t = fma_t(mul_rounded(mul_rounded(R(15), P[2]), P[2]), P[1], t);
-        t = fma_t(mul_rounded(R(20), P[3]), q, t);
-        t = fma_t(mul_rounded(R(-20), P[3]), P[2], t);
-        t = fma_t(mul_rounded(R(-30), P[1]), P[4], t);
-        return R(1.0 / 120.0) * t;
+        // P1^5 - 10 P1^3 P2 + 15 P1 P2^2 + 20 P1^2 P3 - 20 P2 P3 - 30 P1 P4 + 24 P5
+        //   = P1 (P1 (P1 (P1^2 - 10 P2) + 20 P3) + (15 P2^2 - 30 P4)) + (24 P5 - 20 P2 P3)
+        const R p3x20 = mul_rounded(R(20), P[3]);
+        const R a = fma_t(P[1], P[1], mul_rounded(R(-10), P[2]));
+        const R b = fma_t(P[1], a, p3x20);
+        const R c = fma_t(mul_rounded(R(15), P[2]), P[2], mul_rounded(R(-30), P[4]));
+        const R d = fma_t(P[1], b, c);
+        const R f = fma_t(-P[2], p3x20, mul_rounded(R(24), P[5]));
+        return fma_t(P[1], d, f);
     } else {
         R e[N + 1];
         e[0] = R(1);
@@ -394,8 +418,23 @@ __device__ __forceinline__ R newton_girard(const R *P)
     }
 }
 
+template <int N, typename R>
+__device__ __forceinline__ R newton_girard(const R *P)
+{
+    return newton_girard_scaled<N, R>(P) * R(ng_scale(N));
+}
+
+// One output pixel from its sums: y = E_n * CF * in_scale, eqs. (13)/(14).
+// In the FP32 form the 1/n! of the expansions is folded into `out_scale`
+// (in_scale / n!, formed once per kernel by the caller).
+// One output pixel from its sums: y = E_n * CF * in_scale, eqs. (13)/(14).
+// Newton-Girard runs in FP64 for FP64 sums or with the plan's ng_fp64 flag
+// (its result, n! E_n for n <= 5, is rounded to FP32 once the cancellation
+// is done), else in FP32; either way the 1/n! of the expansions is folded
+// into `out_scale` (in_scale / n!, formed once per kernel by the caller).
 template <int N, bool CF, int ACC>
-__device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const KernelParams &p)
+__device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const KernelParams &p,
+                                              float out_scale)
 {
     constexpr bool KAHAN = ACC == kAccKahan;
     float e;
@@ -403,12 +442,12 @@ __device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const 
         double P[N + 1];
 #pragma unroll
         for (int k = 1; k <= N; ++k) P[k] = (double)acc.p[k] - (KAHAN ? (double)acc.cp[KAHAN ? k : 0] : 0.0);
-        e = (float)newton_girard<N, double>(P);
+        e = (float)newton_girard_scaled<N, double>(P);
     } else {
         float P[N + 1];
 #pragma unroll
         for (int k = 1; k <= N; ++k) P[k] = KAHAN ? (float)acc.p[k] - acc.cp[KAHAN ? k : 0] : (float)acc.p[k];
-        e = newton_girard<N, float>(P);
+        e = newton_girard_scaled<N, float>(P);
     }
     if constexpr (CF) {
         float sx = (float)((N & 1) ? acc.p[N] : acc.a);
@@ -420,7 +459,16 @@ __device__ __forceinline__ float finish_pixel(const Acc<N, CF, ACC> &acc, const 
         const float den = __builtin_fmaf((float)p.M, sb, p.cf_eps);
         e = e * (sx * sx) * __builtin_amdgcn_rcpf(den);
     }
-    return e * p.in_scale;
+    return e * out_scale;
+}
+
+// in_scale / n!: the output scale of the FP32 Newton-Girard form (wave-uniform,
+// kept in a scalar register).
+template <int N>
+__device__ __forceinline__ float fp32_out_scale(const KernelParams &p)
+{
+    const float v = p.in_scale * (float)ng_scale(N);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
 }
 
 // ---------------------------------------------------------------------------
@@ -604,10 +652,24 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         // the eight reads use immediate offsets and are issued together. Even
         // steps go to e0, odd ones to e1.
         const float *hq = ha, *rq = rb;
-        int kk = 0;
         // the wave's matrix-core steps first, while the other waves fill the VALU
-        // (raised wave priority: 1.3 % faster at order 5, no change at 3 or 7)
+        // (raised wave priority: 1.3 % faster at order 5, no change at 3 or 7);
+        // ks >= 4. Kernels without a register cap (plain sums, n <= 5) start
+        // the first four steps from zero accumulators; in the others that
+        // raised the spills.
         __builtin_amdgcn_s_setprio(3);
+        int kk = 0;
+        if constexpr (N <= 5 && ACC == kAccF32) {
+            const float a0 = hq[0], a1 = hq[4], a2 = hq[8], a3 = hq[12];
+            const float b0 = rq[0], b1 = rq[4], b2 = rq[8], b3 = rq[12];
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, e1, 0, 0, 0);
+            e0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, e0, 0, 0, 0);
+            e1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b3, e1, 0, 0, 0);
+            kk = 4;
+            hq += 16;
+            rq += 17;
+        }
         for (; kk + 3 < ks; kk += 4, hq += 16, rq += 17) {
             const float a0 = hq[0], a1 = hq[4], a2 = hq[8], a3 = hq[12];
             const float b0 = rq[0], b1 = rq[4], b2 = rq[8], b3 = rq[12];
@@ -653,9 +715,13 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         __builtin_amdgcn_wave_barrier();
     };
 
-    // Power sums: cleared here and right after each epilogue reads them
-    // (clearing them at the top of every pass made the compiler emit the
-    // clears on both sides of the `compute` branch: measured 1.6 % slower).
+    const float out_scale = fp32_out_scale<N>(p);
+
+    // Power sums. Plain FP32 sums (PEEL): each chunk's first microphone starts
+    // them, and they are cleared once here so that envelope-only passes (no
+    // microphones) read defined values. Other sums: cleared here and after
+    // each epilogue.
+    constexpr bool PEEL = ACC == kAccF32;
     Acc<N, CF, ACC> acc[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) acc[j].zero();
@@ -696,15 +762,20 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             // ---- hot loop: delayed samples -> roots -> power sums ----
             if (active) {
                 const int nm = min(p.mic_block, p.M - blk * p.mic_block);
-                // microphone i of the block: its window starts at LDS element off
-                auto mic_step = [&](int i, int off) {
+                // microphone i of the block: its window starts at LDS element off;
+                // the chunk's first microphone starts the sums (no clearing)
+                auto mic_step = [&](auto first, int i, int off) {
+                    constexpr bool FIRST = decltype(first)::value;
                     const Elem *src = xwin + off + lane;
                     if constexpr (ROOTS) {
                         float2 v[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) v[j] = src[kWaveSize * j];
 #pragma unroll
-                        for (int j = 0; j < K; ++j) accumulate_root<N, CF, ACC>(acc[j], v[j].x, v[j].y);
+                        for (int j = 0; j < K; ++j) {
+                            if constexpr (FIRST) accumulate_root_first<N, CF, ACC>(acc[j], v[j].x, v[j].y);
+                            else accumulate_root<N, CF, ACC>(acc[j], v[j].x, v[j].y);
+                        }
                     } else if constexpr (LINEAR) {
                         const float fr = __builtin_bit_cast(
                             float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myfrac_blk), i));
@@ -716,30 +787,50 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                         }
 #pragma unroll
                         for (int j = 0; j < K; ++j)
-                            accumulate<N, CF, ACC>(acc[j], __builtin_fmaf(fr, v1[j] - v0[j], v0[j]));
+                            accumulate<N, CF, ACC, FIRST>(acc[j], __builtin_fmaf(fr, v1[j] - v0[j], v0[j]));
                     } else {
                         float v[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) v[j] = src[kWaveSize * j];
 #pragma unroll
-                        for (int j = 0; j < K; ++j) accumulate<N, CF, ACC>(acc[j], v[j]);
+                        for (int j = 0; j < K; ++j) accumulate<N, CF, ACC, FIRST>(acc[j], v[j]);
                     }
                 };
+                using first_t = std::integral_constant<bool, PEEL>;
+                using rest_t = std::false_type;
+                // microphone 0 of block 0 starts the chunk's sums (block 0 has a
+                // loop of its own from microphone 1: a start index chosen at run
+                // time became a vector register and cost four VALU per microphone)
                 if (table) {
                     // the next microphone's offset is loaded while this one is summed
                     const_i32 *ob = off_row + blk * p.mic_block;
                     int o_next = ob[0];
-                    for (int i = 0; i < nm; ++i) {
+                    auto rest = [&](int i) {
                         const int o = o_next;
                         if (i + 1 < nm) o_next = ob[i + 1];
-                        mic_step(i, o);
+                        mic_step(rest_t{}, i, o);
+                    };
+                    if (PEEL && blk == 0) {
+                        const int o = o_next;
+                        if (nm > 1) o_next = ob[1];
+                        mic_step(first_t{}, 0, o);
+                        for (int i = 1; i < nm; ++i) rest(i);
+                    } else {
+                        for (int i = 0; i < nm; ++i) rest(i);
                     }
                 } else if constexpr (TAB_LANES) {
+                    if (PEEL && blk == 0) mic_step(first_t{}, 0, soff[0]);
+                    else mic_step(rest_t{}, 0, soff[0]);
 #pragma unroll
-                    for (int i = 0; i < LB; ++i)
-                        if (i < nm) mic_step(i, soff[i]);
+                    for (int i = 1; i < LB; ++i)
+                        if (i < nm) mic_step(rest_t{}, i, soff[i]);
                 } else {
-                    for (int i = 0; i < nm; ++i) mic_step(i, __builtin_amdgcn_readlane(myoff, i));
+                    if (PEEL && blk == 0) {
+                        mic_step(first_t{}, 0, __builtin_amdgcn_readlane(myoff, 0));
+                        for (int i = 1; i < nm; ++i) mic_step(rest_t{}, i, __builtin_amdgcn_readlane(myoff, i));
+                    } else {
+                        for (int i = 0; i < nm; ++i) mic_step(rest_t{}, i, __builtin_amdgcn_readlane(myoff, i));
+                    }
                 }
             }
         }
@@ -751,18 +842,21 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
-                const float y = finish_pixel<N, CF, ACC>(acc[j], p);
-                acc[j].zero();
+                const float y = finish_pixel<N, CF, ACC>(acc[j], p, out_scale);
+                if constexpr (!PEEL) acc[j].zero();
                 if (t < g1) __builtin_nontemporal_store(y, p.out + orow + t);
             }
         } else {
+            // |y| of samples [tc, tc + C) into the ring; samples at or past T
+            // (and every sample of an envelope-only pass) enter as zeros.
+            // tc >= 0, so lane + 64 j < lim is the whole test.
+            const int lim = compute ? p.T - tc : 0;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const int t = tc + lane + kWaveSize * j;
-                const float y = finish_pixel<N, CF, ACC>(acc[j], p);
-                acc[j].zero();
+                const float y = finish_pixel<N, CF, ACC>(acc[j], p, out_scale);
+                if constexpr (!PEEL) acc[j].zero();
                 const int ri = env_prefix(H) + lane + kWaveSize * j;
-                ring[ri + (ri >> 4)] = (compute && t >= 0 && t < p.T) ? __builtin_fabsf(y) : 0.0f;
+                ring[ri + (ri >> 4)] = lane < lim - kWaveSize * j ? __builtin_fabsf(y) : 0.0f;
             }
             envelope_pass(tc, orow);
         }
