@@ -209,20 +209,26 @@ __device__ __forceinline__ void stage_row_roots(float2 *__restrict__ dst, const 
                                                 size_t chan, int base, int row, int T, int lane)
 {
     if (base >= 0 && base + row <= T) {
-        const float2 *src = plane + chan + (size_t)base + lane;
+        // The window's start is wave-uniform and each lane adds a 32-bit byte
+        // offset, so the loads take a scalar base address and the per-row
+        // address arithmetic stays on the scalar unit.
+        const char *src = reinterpret_cast<const char *>(plane + chan + (size_t)base);
+        auto at = [&](int r) {
+            const unsigned off = (unsigned)lane * 8u + (unsigned)r * (8u * kWaveSize);
+            return *reinterpret_cast<const float2 *>(src + off);
+        };
         float2 *d = dst + lane;
         const int full = row / kWaveSize;   // whole wave-wide steps (wave-uniform)
         int r = 0;
         for (; r + 4 <= full; r += 4) {
-            const float2 a0 = src[(r + 0) * kWaveSize], a1 = src[(r + 1) * kWaveSize];
-            const float2 a2 = src[(r + 2) * kWaveSize], a3 = src[(r + 3) * kWaveSize];
+            const float2 a0 = at(r + 0), a1 = at(r + 1), a2 = at(r + 2), a3 = at(r + 3);
             d[(r + 0) * kWaveSize] = a0;
             d[(r + 1) * kWaveSize] = a1;
             d[(r + 2) * kWaveSize] = a2;
             d[(r + 3) * kWaveSize] = a3;
         }
-        for (; r < full; ++r) d[r * kWaveSize] = src[r * kWaveSize];
-        if (lane < row - full * kWaveSize) d[full * kWaveSize] = src[full * kWaveSize];
+        for (; r < full; ++r) d[r * kWaveSize] = at(r);
+        if (lane < row - full * kWaveSize) d[full * kWaveSize] = at(full);
     } else {
         for (int r = lane; r < row; r += kWaveSize) {
             const int t = base + r;
