@@ -714,7 +714,12 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
     p->row = (p->row + 3) & ~3;
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
-    const size_t ring_bytes = sizeof(float) * (size_t)dmas::env_lds_floats(H, W);
+    // envelope: taps, then per-wave rings, or with more microphones than lanes
+    // per-wave carries while the rings share the window region
+    const bool share = dmas::rings_share_windows(M);
+    const size_t ring_bytes = sizeof(float) * (size_t)W * dmas::ring_stride(H);
+    const size_t env_side = sizeof(float) * (size_t)(dmas::env_taps_len(H) +
+                                                     W * (share ? dmas::carry_stride(H) : dmas::ring_stride(H)));
     const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
     // Microphones per LDS block: the largest block whose footprint lets three
     // workgroups share a CU (else two, else one). More blocks cost barriers and
@@ -722,7 +727,10 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // Window elements: (root, sample) pairs when the kernel stages roots
     // (whole-sample delays, n >= 2), else samples.
     const size_t elem = p->roots ? 2 * sizeof(float) : sizeof(float);
-    auto lds_for = [&](int m) { return fixed + ring_bytes + elem * (size_t)m * p->row; };
+    auto lds_for = [&](int m, bool env = true) {
+        const size_t win = elem * (size_t)m * p->row;
+        return fixed + (env ? (share ? std::max(win, ring_bytes) : win) + env_side : win);
+    };
     // Per-tile delay tables for whole-sample delays, when of modest size (the
     // delay mode selects the kernel, so it is fixed before the occupancy
     // queries below).
@@ -769,8 +777,14 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
                     "direction tiles spread over %d samples: the channel window does not fit in LDS", p->halo);
     }
     p->mic_block = mb;
-    p->lds_rf = fixed + elem * (size_t)mb * p->row;
-    p->lds_env = p->lds_rf + ring_bytes;
+    p->lds_rf = lds_for(mb, false);
+    p->lds_env = lds_for(mb, true);
+    // the kernel derives the same layout from (mic_block, row, H)
+    if (p->lds_env != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), true, H, share) ||
+        p->lds_rf != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), false, H, share)) {
+        plan_free(p);
+        return fail(DMAS_ERR_DEVICE, "internal: LDS layout mismatch");
+    }
 
     // Build the delay tables: the kernel reads window offsets and reference
     // delays instead of evaluating eq. (1) on the device and moving the

@@ -12,9 +12,9 @@ constexpr int kWaveSize = 64;
 constexpr int kMaxOrder = 8;
 constexpr int kMaxMicBlock = 64;   // microphones staged in LDS at once (<= wave size)
 // Microphones per block with kDelayTableLanes (a block's offsets are read as
-// one scalar block into SGPRs): 12 for orders up to 3, whose kernels have the
-// SGPR budget of eight waves per SIMD, else 16.
-__host__ __device__ constexpr int lane_block_max(int order) { return order <= 3 ? 12 : 16; }
+// one scalar block into SGPRs): 16 for every order (the order-3 kernels, which
+// run eight waves per SIMD, hold them within their SGPR budget).
+__host__ __device__ constexpr int lane_block_max(int) { return 16; }
 constexpr int kLaneBlockMax = 16;  // the largest, for padding the tables
 
 // Everything a beamforming launch needs, passed by value as the kernel argument.
@@ -89,10 +89,15 @@ constexpr int kChunk = kWaveSize * kSamplesPerLane;
 __host__ __device__ constexpr int env_lead(int H) { return (H + 31) & ~31; }
 __host__ __device__ constexpr int env_prefix(int H) { return H + env_lead(H); }
 
-// Envelope LDS of a workgroup (floats), after the windows and reference
-// delays: a taps table of env_taps_len(H) floats (kTapLead zeros, the L =
-// 2H + 1 taps in reverse order, zeros), then one ring per wave of
-// ring_stride(H) floats. The
+// Envelope LDS of a workgroup: after the channel windows come the reference
+// delays (kMaxMicBlock ints), a taps table of env_taps_len(H) floats (kTapLead
+// zeros, the L = 2H + 1 taps in reverse order, zeros) and one ring per wave of
+// ring_stride(H) floats. With more microphones than lanes (many blocks per
+// chunk, where LDS decides the block size) the rings instead share the window
+// region, which they need only in the epilogue after the chunk's last block:
+// the region then holds max(windows, kDirsPerTile rings), and per wave
+// carry_stride(H) floats after the taps keep the env_prefix(H) values of |y|
+// carried from one chunk to the next while the windows occupy the region. A
 // ring holds |y| for ring index i in [0, env_prefix(H) + kChunk) at float
 // i + i / 16; the skew keeps the FIR's matrix-operand reads (16 indices 16
 // apart) on distinct LDS banks. The FIR is a product with K = 2H + 16 in steps
@@ -105,7 +110,25 @@ __host__ __device__ constexpr int ring_logical(int H)
     return kChunk + (env_prefix(H) > 2 * H + 8 ? env_prefix(H) : 2 * H + 8);
 }
 __host__ __device__ constexpr int ring_stride(int H) { return (ring_logical(H) + ring_logical(H) / 16 + 1 + 3) & ~3; }
-__host__ __device__ constexpr int env_lds_floats(int H, int waves) { return env_taps_len(H) + waves * ring_stride(H); }
+__host__ __device__ constexpr int carry_stride(int H) { return (env_prefix(H) + 3) & ~3; }
+// Whether the envelope rings share the window region (M microphones).
+__host__ __device__ constexpr bool rings_share_windows(int M) { return M > kWaveSize; }
+// Floats of the window region: mic_block rows of `row` elements of elem_floats
+// floats, or the rings if they share it and need more.
+__host__ __device__ constexpr int window_region_floats(int mic_block, int row, int elem_floats, bool env, int H,
+                                                       bool share)
+{
+    return env && share && kDirsPerTile * ring_stride(H) > mic_block * row * elem_floats
+               ? kDirsPerTile * ring_stride(H)
+               : mic_block * row * elem_floats;
+}
+// Dynamic LDS bytes of a workgroup.
+__host__ __device__ constexpr int kernel_lds_bytes(int mic_block, int row, int elem_floats, bool env, int H,
+                                                   bool share)
+{
+    return 4 * (window_region_floats(mic_block, row, elem_floats, env, H, share) + kMaxMicBlock +
+                (env ? env_taps_len(H) + kDirsPerTile * (share ? carry_stride(H) : ring_stride(H)) : 0));
+}
 // Envelope taps on the device: fir_len taps, zero-padded to a multiple of 4.
 __host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; }
 

@@ -505,10 +505,18 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     using Elem = typename std::conditional<ROOTS, float2, float>::type;
 
     const int H = ENV ? (p.fir_len - 1) / 2 : 0;
-    Elem *xwin = reinterpret_cast<Elem *>(smem);                   // mic_block x row
-    int *dref_lds = reinterpret_cast<int *>(xwin + p.mic_block * p.row);  // kMaxMicBlock
+    // LDS: the window region (mic_block x row windows; with `share` also the
+    // per-wave rings in the envelope epilogue), reference delays, taps table,
+    // then per wave either its ring or (share) the |y| it carries between chunks
+    const bool share = ENV && rings_share_windows(p.M);
+    const int region = window_region_floats(p.mic_block, p.row, ROOTS ? 2 : 1, ENV, H, share);
+    Elem *xwin = reinterpret_cast<Elem *>(smem);                             // mic_block x row
+    int *dref_lds = reinterpret_cast<int *>(smem + region);                  // kMaxMicBlock
     float *tap_lds = reinterpret_cast<float *>(dref_lds + kMaxMicBlock);     // env_taps_len(H)
-    float *ring = tap_lds + env_taps_len(H) + wave * ring_stride(H);         // |y| of index i at i + i/16
+    float *side = tap_lds + env_taps_len(H);
+    float *carry = side + wave * carry_stride(H);                            // share: |y| kept between chunks
+    float *ring = share ? smem + wave * ring_stride(H)                       // |y| of index i at i + i/16
+                        : side + wave * ring_stride(H);
 
     const int dir = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W + wave]);
     const int dir0 = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W]);
@@ -554,9 +562,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const_i32 *off_row = table ? reinterpret_cast<const_i32 *>(
                                      reinterpret_cast<uintptr_t>(p.tile_off + ((size_t)tile * W + wave) * p.M))
                                : nullptr;
-    const_i32 *dref_row = table ? reinterpret_cast<const_i32 *>(
-                                      reinterpret_cast<uintptr_t>(p.tile_dref + (size_t)tile * p.M))
-                                : nullptr;
+    const_i32 *dref_row = (table || TAB_LANES) ? reinterpret_cast<const_i32 *>(
+                                                     reinterpret_cast<uintptr_t>(p.tile_dref + (size_t)tile * p.M))
+                                               : nullptr;
     const int32_t *off_lanes = TAB_LANES ? p.tile_off + ((size_t)tile * W + wave) * p.M : nullptr;
     // tables for more than 64 microphones: the block's window offsets of this wave's direction,
     // loaded as one scalar block before the block's barrier (mic_block <= 16;
@@ -564,8 +572,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const_i32 *off_srow = TAB_LANES ? reinterpret_cast<const_i32 *>(reinterpret_cast<uintptr_t>(off_lanes)) : nullptr;
     constexpr int LB = lane_block_max(N);
     int soff[LB];
-    const int32_t *dref_lanes = TAB_LANES ? p.tile_dref + (size_t)tile * p.M : nullptr;
-    int mydref = 0;           // reference delay of microphone `lane` of the block (TAB_LANES)
+    // TAB_LANES: reference delays of the (at most two: mic_block <= 2 W) rows
+    // this wave stages, wave and wave + W of the block
+    int sdref0 = 0, sdref1 = 0;
     int mydw = 0;
     int myoff = 0;
     float myfrac = 0.0f;      // fraction of mydw's microphone (linear delays)
@@ -574,11 +583,13 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         if (table) return;
         const int mic = blk * p.mic_block + lane;
         if constexpr (TAB_LANES) {
-            // issued before the block's barrier so the loads overlap the wait
-            if (lane < p.mic_block && mic < p.M) mydref = dref_lanes[mic];
+            // scalar loads issued before the block's barrier so they overlap the wait
             const_i32 *ob = off_srow + blk * p.mic_block;
 #pragma unroll
             for (int k = 0; k < LB; ++k) soff[k] = ob[k];
+            const int r0 = blk * p.mic_block + wave;
+            sdref0 = (wave < p.mic_block && r0 < p.M) ? dref_row[r0] : 0;
+            sdref1 = (wave + W < p.mic_block && r0 + W < p.M) ? dref_row[r0 + W] : 0;
             return;
         }
         const int nlanes = all_mics ? p.M : p.mic_block;
@@ -593,7 +604,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     };
     // Reference delay of microphone i (wave-uniform) of block blk, for staging.
     auto dref_of = [&](int blk, int i) {
-        if constexpr (TAB_LANES) return __builtin_amdgcn_readlane(mydref, i);
+        if constexpr (TAB_LANES) return i == wave ? sdref0 : sdref1;
         return table ? dref_row[blk * p.mic_block + i] : dref_lds[all_mics ? blk * p.mic_block + i : i];
     };
     auto block_offsets = [&](int blk) {
@@ -622,7 +633,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 
     if (all_mics) block_geometry(0);
     if constexpr (ENV) {
-        for (int i = lane; i < ring_stride(H); i += kWaveSize) ring[i] = 0.0f;
+        if (share) {
+            for (int i = lane; i < carry_stride(H); i += kWaveSize) carry[i] = 0.0f;
+        } else {
+            for (int i = lane; i < ring_stride(H); i += kWaveSize) ring[i] = 0.0f;
+        }
         for (int j = tx; j < env_taps_len(H); j += W * kWaveSize) {
             const int k = j - kTapLead;   // reversed: entry kTapLead + k holds h[2H - k]
             tap_lds[j] = (k >= 0 && k <= 2 * H) ? taps[2 * H - k] : 0.0f;
@@ -713,10 +728,15 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                 __builtin_nontemporal_store(ev, p.out + orow + j);
             }
         }
+        // keep the last env_prefix(H) values of |y| for the next pass: in the
+        // carry when the windows take the ring's region until then, else at the
+        // ring's start (<= C: no overlap)
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // keep the last env_prefix(H) values of |y| for the next pass (<= C: no overlap)
-        for (int i = lane; i < env_prefix(H); i += kWaveSize) ring[i + (i >> 4)] = ring[C + i + ((C + i) >> 4)];
+        float *keep = share ? carry : ring;
+        const int skew = share ? 0 : 1;
+        for (int i = lane; i < env_prefix(H); i += kWaveSize)
+            keep[i + skew * (i >> 4)] = ring[C + i + ((C + i) >> 4)];
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     };
@@ -841,6 +861,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             }
         }
 
+        // rings in the window region: every wave (active or not) has read its
+        // last window before any ring is written
+        if (share) __syncthreads();
         if (!active) continue;
         // ---- epilogue: Newton-Girard, CF, store or envelope ----
         const size_t orow = (size_t)dir * (size_t)p.out_T;
@@ -853,9 +876,14 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                 if (t < g1) __builtin_nontemporal_store(y, p.out + orow + t);
             }
         } else {
-            // |y| of samples [tc, tc + C) into the ring; samples at or past T
-            // (and every sample of an envelope-only pass) enter as zeros.
-            // tc >= 0, so lane + 64 j < lim is the whole test.
+            // ring: the carried prefix, |y| of samples [tc, tc + C), zeros after
+            // them. Samples at or past T (and every sample of an envelope-only
+            // pass) enter as zeros; tc >= 0, so lane + 64 j < lim is the whole test.
+            if (share) {
+                for (int i = lane; i < env_prefix(H); i += kWaveSize) ring[i + (i >> 4)] = carry[i];
+                for (int i = env_prefix(H) + C + lane; i < ring_logical(H); i += kWaveSize)
+                    ring[i + (i >> 4)] = 0.0f;
+            }
             const int lim = compute ? p.T - tc : 0;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
