@@ -384,6 +384,61 @@ def random_frame(rng: np.random.Generator, M: int, D: int, T: int, order: int,
 
 
 
+def point_scene_frame(mics: np.ndarray, reflectors: Sequence[tuple], az_deg: Sequence[float],
+                      num_samples: int, lead_samples: int, snr_db: Optional[float] = None,
+                      stream: int = 7, seed_salt: int = 0, order: int = 5, name: str = "scene") -> Frame:
+    """Point reflectors in the horizontal plane imaged by ``mics`` (Section III-A simulations).
+
+    ``reflectors`` holds (azimuth in degrees, range in metres, amplitude) at
+    elevation 0. An emitter at the origin sends the 25-75 kHz chirp of 1 ms; the
+    echo of reflector p reaches microphone i after (|p| + |p - r_i|)/c with the
+    given amplitude in every channel (no spreading loss, the paper's
+    normalisation of a unit echo), placed by linear interpolation of the sampled
+    chirp. The record starts ``lead_samples`` after emission. With ``snr_db``
+    white noise of standard deviation 10**(-snr_db/20) is added before matched
+    filtering, eqs. (15)-(16). Directions: the azimuths ``az_deg`` at elevation 0.
+    """
+    rng = rng_for(stream, seed_salt)
+    fs, c, T = 450e3, SPEED_OF_SOUND, num_samples
+    M = mics.shape[0]
+    pulse = linear_chirp(fs, 25e3, 75e3, 1e-3)
+    raw = np.zeros((M, T))
+    onsets = []
+    for az, rng_m, amp in reflectors:
+        p = rng_m * unit_vectors(az, 0.0)
+        dist = np.linalg.norm(p) + np.linalg.norm(p[None, :] - mics, axis=1)
+        for i in range(M):
+            place_fractional(raw[i], pulse, fs * dist[i] / c - lead_samples, amp)
+        onsets.append(int(round(fs * 2.0 * rng_m / c)) - lead_samples)
+    if snr_db is not None:
+        raw += rng.standard_normal(raw.shape) * 10 ** (-snr_db / 20.0)
+    x = matched_filter(raw, pulse)
+    az = np.asarray(az_deg, dtype=np.float64)
+    return Frame(name, x, mics, az_el_grid(az, [0.0]), fs, c, order, True, False,
+                 truth=dict(az=az, reflectors=list(reflectors), onsets=onsets, pulse_len=pulse.size))
+
+
+def two_reflector_frame(half_angle_deg: float, order: int = 5, az_step: float = 0.25) -> Frame:
+    """Two unit reflectors at 1.5 m, symmetric about the forward axis at azimuths +-half_angle
+    (the spatial-resolution experiment of Section III-A), seen by the 32-microphone 12 cm disc
+    of ``point_echo_frame``; azimuths -30..30 deg, 1024 samples with the echoes near sample 300."""
+    mics = disc_array(np.random.default_rng(SEED_BASE + 6), 32, 0.12, min_spacing=0.004)
+    lead = int(round(450e3 * 2.0 * 1.5 / SPEED_OF_SOUND)) - 300
+    refl = [(-half_angle_deg, 1.5, 1.0), (half_angle_deg, 1.5, 1.0)]
+    return point_scene_frame(mics, refl, np.arange(-30.0, 30.0 + 1e-9, az_step), 1024, lead,
+                             stream=8, order=order, name="two_reflectors")
+
+
+def hex_psf_frame(radius: float, order: int = 5, az_step: float = 0.25) -> Frame:
+    """Noise-free broadside reflector at 1 m seen by a hexagonal-lattice disc array of 5 mm edge and
+    the given radius (the beamwidth experiment of Section III-A, 19-513 microphones for radii of
+    1-6 cm); azimuths -45..45 deg, 1024 samples with the echo near sample 300."""
+    mics = hex_disc_array(radius, 0.005)
+    lead = int(round(450e3 * 2.0 / SPEED_OF_SOUND)) - 300
+    return point_scene_frame(mics, [(0.0, 1.0, 1.0)], np.arange(-45.0, 45.0 + 1e-9, az_step), 1024, lead,
+                             stream=9, order=order, name=f"hex_r{radius * 100:.0f}cm")
+
+
 def point_echo_frame(order: int = 5, snr_db: Optional[float] = None, seed_salt: int = 0,
                      num_samples: int = 2048, az_step: float = 1.0, lead_samples: int = 600) -> Frame:
     """Single point reflector at 1 m broadside, for point-spread and image-SNR studies.
