@@ -139,6 +139,9 @@ typedef struct {
     int64_t workgroups;        /* per launch */
     int64_t delay_table_bytes; /* device memory of the plan's per-tile delay tables
                                   (0: delays are evaluated on the device) */
+    int64_t device_bytes;      /* all device memory the plan holds (geometry, taps,
+                                  tiling, delay tables); a server counts it against
+                                  its HBM budget */
 } dmas_plan_info_t;
 
 /* Fill *desc with defaults: far field, FP32 input, CF on, nearest delays,
@@ -239,7 +242,9 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  *   - submit copies the frame's input into pinned staging memory and queues it;
  *   - a scheduler thread admits queued frames in arrival order while their
  *     device input, root plane (M*T*8 bytes, plans with whole-sample delays
- *     and n >= 2) and output fit in the HBM budget (an arena allocated once),
+ *     and n >= 2) and output fit in the HBM budget (an arena allocated once;
+ *     the plan's own device memory is counted there too while any frame of
+ *     the plan holds device memory),
  *     copies the input and fills the root plane on a copy stream, and groups
  *     admitted frames into one
  *     multi-frame launch (frames with the same CF / envelope / geometry flags,
@@ -316,7 +321,8 @@ dmas_status_t dmas_server_create(const dmas_server_desc_t *desc, dmas_server_t *
 
 /* Queue one frame. h_x: host memory, M x T of the plan's in_dtype, copied
  * before return. arrival: the request's arrival time for latency accounting
- * (< 0: now). A frame whose input + root plane + output exceed the budget is
+ * (< 0: now). A frame whose input + root plane + output, plus its plan's
+ * device memory (dmas_plan_info_t.device_bytes), exceed the budget is
  * DMAS_ERR_INVALID_ARG; full staging is DMAS_ERR_BUSY (nothing queued). */
 dmas_status_t dmas_server_submit(dmas_server_t srv, dmas_plan_t plan, const void *h_x, float in_scale,
                                  int32_t flags, double arrival, uint64_t *ticket);

@@ -49,6 +49,7 @@ struct dmas_plan_s {
     int env_decim = 1;
     int mf_len = 0;
     float *d_pulse = nullptr;
+    size_t device_bytes = 0;   // all device memory the plan holds (geometry, taps, tiles, tables)
 };
 
 namespace dmas {

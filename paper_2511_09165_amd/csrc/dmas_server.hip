@@ -25,16 +25,15 @@
 #include "dmas_internal.hpp"
 #include "dmas_plan.hpp"
 #include "dmas_resident.hpp"
+#include "dmas_sched.hpp"
 
 namespace {
 
-constexpr size_t kAlign = 256;
 constexpr int kMaxBatchFrames = 1024;
 
-size_t align_up(size_t v)
-{
-    return (v + kAlign - 1) & ~(kAlign - 1);
-}
+using dmas::sched::Arena;
+using dmas::sched::align_up;
+using dmas::sched::kAlign;
 
 double now_s()
 {
@@ -51,58 +50,6 @@ std::chrono::steady_clock::time_point deadline_after(double timeout)
     const double t = std::min(timeout, kMaxWait);
     return steady_clock::now() + duration_cast<steady_clock::duration>(duration<double>(t));
 }
-
-// First-fit allocator over [0, size) with coalescing of free ranges.
-class Arena {
-public:
-    void reset(size_t size)
-    {
-        free_.clear();
-        if (size) free_[0] = size;
-        size_ = size;
-        used_ = 0;
-    }
-    bool alloc(size_t bytes, size_t *off)
-    {
-        bytes = align_up(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = align_up(bytes);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-
-private:
-    std::map<size_t, size_t> free_;
-    size_t size_ = 0, used_ = 0;
-};
 
 enum FrameState { kQueued = 0, kAdmitted = 1, kLaunched = 2, kDone = 3, kFailed = -1 };
 
@@ -157,12 +104,12 @@ bool batchable(const dmas_plan_s *p)
     return !p->linear && !p->compensated;
 }
 
-// Frames that can share one multi-frame launch (same kernel instantiation).
-bool same_class(const Frame *a, const Frame *b)
+// Kernel class of a frame: frames of one class can share a multi-frame
+// launch (same kernel instantiation).
+int64_t kernel_class(const Frame *f)
 {
-    return a->env == b->env && a->plan->order == b->plan->order && a->plan->cf == b->plan->cf &&
-           a->plan->nearfield == b->plan->nearfield &&
-           dmas::shape_of(a->plan, a->env).delay == dmas::shape_of(b->plan, b->env).delay;
+    return (int64_t)f->env | (int64_t)f->plan->cf << 1 | (int64_t)f->plan->nearfield << 2 |
+           (int64_t)dmas::shape_of(f->plan, f->env).delay << 3 | (int64_t)f->plan->order << 8;
 }
 
 dmas_status_t srv_fail(dmas_status_t st, const char *msg)
@@ -223,6 +170,13 @@ struct dmas_server_s {
     std::vector<hipEvent_t> event_pool;
 
     std::deque<Frame *> queued, admitted;
+    // Plans with frames holding device memory: the plan's own device memory is
+    // counted in the budget (an arena range) while any of its frames is.
+    struct PlanUse {
+        size_t off, bytes;
+        int frames;
+    };
+    std::unordered_map<uint64_t, PlanUse> plan_use;   // by plan serial
     std::unordered_map<uint64_t, Frame *> frames;
     std::deque<dmas_frame_info_t> finished;   // records of auto-released frames
     uint64_t next_ticket = 1;
@@ -300,6 +254,11 @@ struct dmas_server_s {
         if (f->in_dev_bytes) arena_free(f->in_off, f->in_dev_bytes);
         arena_free(f->out_off, f->out_bytes);
         if (f->plane_bytes) arena_free(f->plane_off, f->plane_bytes);
+        auto pu = plan_use.find(f->plan->serial);
+        if (pu != plan_use.end() && --pu->second.frames == 0) {
+            if (pu->second.bytes) arena_free(pu->second.off, pu->second.bytes);
+            plan_use.erase(pu);
+        }
         f->on_device = false;
     }
 
@@ -398,22 +357,22 @@ struct dmas_server_s {
             // and output only, and needs no copy.
             const bool resident = res_on && resident_capable(f->plan, f->env);
             const size_t in_dev = resident ? 0 : f->in_bytes;
-            size_t in_off = 0, out_off = 0, plane_off = 0;
-            if (in_dev && !arena.alloc(in_dev, &in_off)) break;
-            if (!arena.alloc(f->out_bytes, &out_off)) {
-                if (in_dev) arena.release(in_off, in_dev);
+            // arrival order: the first frame that does not fit stops admission; a
+            // frame whose plan has no other frame holding device memory also
+            // reserves the plan's device memory
+            auto pu = plan_use.find(f->plan->serial);
+            const bool new_plan = pu == plan_use.end();
+            dmas::sched::Grant g;
+            if (!dmas::sched::grant(arena, in_dev, f->out_bytes, f->plane_bytes,
+                                    new_plan ? f->plan->device_bytes : 0, &g))
                 break;
-            }
-            if (f->plane_bytes && !arena.alloc(f->plane_bytes, &plane_off)) {
-                if (in_dev) arena.release(in_off, in_dev);
-                arena.release(out_off, f->out_bytes);
-                break;
-            }
+            if (new_plan) pu = plan_use.emplace(f->plan->serial, PlanUse{g.plan_off, f->plan->device_bytes, 0}).first;
+            ++pu->second.frames;
             f->resident = resident;
             f->in_dev_bytes = in_dev;
-            f->in_off = in_off;
-            f->out_off = out_off;
-            f->plane_off = plane_off;
+            f->in_off = g.in_off;
+            f->out_off = g.out_off;
+            f->plane_off = g.plane_off;
             f->on_device = true;
             hbm_peak = std::max(hbm_peak, arena.used());
             f->t_admit = now_s();
@@ -426,9 +385,9 @@ struct dmas_server_s {
             }
             f->copied = get_event();
             // input copy, then the root plane, on the copy stream
-            hipError_t e = hipMemcpyAsync(d_arena + in_off, h_staging + f->stage_off, f->in_bytes,
+            hipError_t e = hipMemcpyAsync(d_arena + f->in_off, h_staging + f->stage_off, f->in_bytes,
                                           hipMemcpyHostToDevice, copy_stream);
-            if (e == hipSuccess && f->plane_bytes) e = dmas::stage_roots(f->plan, d_arena + in_off, plane_of(f), copy_stream);
+            if (e == hipSuccess && f->plane_bytes) e = dmas::stage_roots(f->plan, d_arena + f->in_off, plane_of(f), copy_stream);
             if (e == hipSuccess && f->copied) e = hipEventRecord(f->copied, copy_stream);
             if (e != hipSuccess || !f->copied) {
                 (void)hipStreamSynchronize(copy_stream);   // done with the staging and arena ranges
@@ -450,41 +409,25 @@ struct dmas_server_s {
         while (!admitted.empty()) {
             // A new launch may overlap running ones only in their predicted last
             // device round: overlapping their main body would only slow them down.
-            const double t_now = now_s();
-            int s = -1;
-            bool blocked = false;
-            for (int i = 0; i < nstreams; ++i) {
-                if (launches[i].busy) {
-                    if (t_now < launches[i].tail_start) blocked = true;
-                } else if (s < 0) {
-                    s = i;
-                }
-            }
-            if (s < 0 || blocked) break;
+            std::vector<dmas::sched::StreamState> ss(nstreams);
+            for (int i = 0; i < nstreams; ++i) ss[i] = {launches[i].busy, launches[i].tail_start};
+            const int s = dmas::sched::pick_stream(ss, now_s());
+            if (s < 0) break;
             Launch &l = launches[s];
             hipStream_t st = streams[s];
             Frame *head = admitted.front();
-            std::vector<Frame *> group;
             // Frames that fill the device by themselves go alone; smaller frames of
             // the same kernel class are packed, in arrival order, up to about two
             // device rounds of workgroups.
-            const int64_t head_wgs = dmas::plan_workgroups(head->plan, head->env);
-            if (max_batch > 1 && batchable(head->plan) && head_wgs < batch_wg_cap) {
-                int64_t wgs = 0;
-                for (auto it = admitted.begin(); it != admitted.end() && (int)group.size() < max_batch;) {
-                    Frame *f = *it;
-                    const int64_t fw = dmas::plan_workgroups(f->plan, f->env);
-                    if (batchable(f->plan) && same_class(head, f) && (group.empty() || wgs + fw <= batch_wg_cap)) {
-                        group.push_back(f);
-                        wgs += fw;
-                        it = admitted.erase(it);
-                    } else {
-                        ++it;
-                    }
-                }
-            } else {
-                group.push_back(head);
-                admitted.pop_front();
+            std::vector<dmas::sched::Candidate> cand;
+            cand.reserve(admitted.size());
+            for (Frame *f : admitted)
+                cand.push_back({kernel_class(f), batchable(f->plan), dmas::plan_workgroups(f->plan, f->env)});
+            const std::vector<size_t> pick = dmas::sched::pick_group(cand, max_batch, batch_wg_cap);
+            std::vector<Frame *> group;
+            for (size_t k = pick.size(); k-- > 0;) {   // erase from the back so indices stay valid
+                group.insert(group.begin(), admitted[pick[k]]);
+                admitted.erase(admitted.begin() + (std::ptrdiff_t)pick[k]);
             }
             hipError_t e = hipSuccess;
             for (Frame *f : group)
@@ -965,9 +908,11 @@ dmas_status_t dmas_server_submit(dmas_server_t s, dmas_plan_t plan, const void *
     const size_t out_T = f->env ? (size_t)(plan->T + plan->env_decim - 1) / plan->env_decim : (size_t)plan->T;
     f->out_bytes = (size_t)plan->D * out_T * sizeof(float);
     f->plane_bytes = dmas::plane_bytes(plan);
-    if (align_up(f->in_bytes) + align_up(f->out_bytes) + align_up(f->plane_bytes) > s->budget) {
+    if (!dmas::sched::admissible(f->in_bytes, f->out_bytes, f->plane_bytes, plan->device_bytes, s->budget)) {
         delete f;
-        return srv_fail(DMAS_ERR_INVALID_ARG, "frame input, root plane and output exceed the server's HBM budget");
+        return srv_fail(DMAS_ERR_INVALID_ARG,
+                        "frame input, root plane and output with the plan's device memory exceed the server's HBM "
+                        "budget");
     }
     if (align_up(f->in_bytes) > s->staging) {
         delete f;

@@ -54,7 +54,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in (
         "num_mics", "num_samples", "num_dirs", "order", "dirs_per_tile", "num_tiles", "samples_per_lane",
         "chunk", "segment", "num_segments", "window_halo", "mics_per_block", "lds_bytes", "fir_len")]
-    _fields_ += [("workgroups", ctypes.c_int64), ("delay_table_bytes", ctypes.c_int64)]
+    _fields_ += [("workgroups", ctypes.c_int64), ("delay_table_bytes", ctypes.c_int64),
+                 ("device_bytes", ctypes.c_int64)]
 
 
 class ServerDesc(ctypes.Structure):

@@ -121,9 +121,9 @@ def test_budget_limits_admission():
     frames = _mix(2, 8)
     plans = [plan_for_frame(f) for f in frames]
     alone = [_standalone(p, f.x_f32(), f.env) for f, p in zip(frames, plans)]
-    # input, root plane ((root, sample) FP32 pairs for n >= 2) and output
+    # input, root plane ((root, sample) FP32 pairs for n >= 2), output and the plan's device memory
     need = max(f.num_mics * f.num_samples * (4 + (8 if f.order >= 2 else 0)) + f.num_dirs * f.num_samples * 4
-               for f in frames)
+               + p.info()["device_bytes"] for f, p in zip(frames, plans))
     budget = 2 * need + 4096
     _say(f"serving: budget {budget} bytes")
     outs, infos, stats = _run_server(frames, plans, hbm_budget=budget, num_streams=2, max_batch=64)
