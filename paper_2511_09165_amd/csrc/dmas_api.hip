@@ -21,6 +21,7 @@
 #include "dmas_internal.hpp"
 #include "dmas_kernel.hpp"
 #include "dmas_plan.hpp"
+#include "dmas_validate.hpp"
 
 namespace {
 
@@ -46,13 +47,6 @@ dmas_status_t hip_fail(hipError_t e, const char *what)
 {
     return fail(e == hipErrorOutOfMemory ? DMAS_ERR_OUT_OF_MEMORY : DMAS_ERR_DEVICE, "%s: %s", what,
                 hipGetErrorString(e));
-}
-
-bool finite_all(const double *v, size_t n)
-{
-    for (size_t i = 0; i < n; ++i)
-        if (!std::isfinite(v[i])) return false;
-    return true;
 }
 
 // 10-bit-per-axis Morton key of a point scaled into [0, 1]^3.
@@ -551,78 +545,13 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
 {
     if (!d || !out) return fail(DMAS_ERR_INVALID_ARG, "desc or out is NULL");
     *out = nullptr;
+    char msg[512];
+    dmas::DescValues vals;
+    const dmas_status_t vst = dmas::validate_desc(d, dmas::kChunk, msg, sizeof msg, &vals);
+    if (vst != DMAS_OK) return fail(vst, "%s", msg);
     const int M = d->num_mics, T = d->num_samples, D = d->num_dirs, n = d->order;
-    if (M < 1 || T < 1 || D < 1)
-        return fail(DMAS_ERR_INVALID_ARG, "sizes must be >= 1 (M=%d T=%d D=%d)", M, T, D);
-    if (n < 1 || n > DMAS_MAX_ORDER) return fail(DMAS_ERR_INVALID_ARG, "order %d outside 1..%d", n, DMAS_MAX_ORDER);
-    if (n > M) return fail(DMAS_ERR_INVALID_ARG, "order %d exceeds the number of microphones %d", n, M);
-    if ((int64_t)T + 2 * DMAS_MAX_FIR_LEN + 4 * dmas::kChunk > INT32_MAX / 2)
-        return fail(DMAS_ERR_INVALID_ARG, "num_samples %d too large", T);
-    if (!d->mic_pos || !d->dirs) return fail(DMAS_ERR_INVALID_ARG, "mic_pos or dirs is NULL");
-    if (d->use_cf != 0 && d->use_cf != 1) return fail(DMAS_ERR_INVALID_ARG, "use_cf must be 0 or 1");
-    if (d->geometry != DMAS_FARFIELD && d->geometry != DMAS_NEARFIELD)
-        return fail(DMAS_ERR_INVALID_ARG, "unknown geometry %d", d->geometry);
-    if (d->in_dtype != DMAS_F32 && d->in_dtype != DMAS_F16 && d->in_dtype != DMAS_BF16)
-        return fail(DMAS_ERR_INVALID_ARG, "unknown in_dtype %d", d->in_dtype);
-    if (d->delay_mode != DMAS_DELAY_NEAREST && d->delay_mode != DMAS_DELAY_LINEAR)
-        return fail(DMAS_ERR_INVALID_ARG, "unknown delay_mode %d", d->delay_mode);
-    if (d->ng_fp64 != 0 && d->ng_fp64 != 1) return fail(DMAS_ERR_INVALID_ARG, "ng_fp64 must be 0 or 1");
-    if (d->compensated < DMAS_ACCUM_F32 || d->compensated > DMAS_ACCUM_F64)
-        return fail(DMAS_ERR_INVALID_ARG, "compensated must be 0 (FP32), 1 (Kahan) or 2 (FP64)");
-    if (!(d->fs > 0.0) || !std::isfinite(d->fs)) return fail(DMAS_ERR_INVALID_ARG, "fs must be > 0");
-    const double c = d->c == 0.0 ? 343.0 : d->c;
-    if (!(c > 0.0) || !std::isfinite(c)) return fail(DMAS_ERR_INVALID_ARG, "c must be > 0");
-    const double eps = d->cf_eps == 0.0 ? 1e-20 : d->cf_eps;
-    if (!(eps > 0.0) || !std::isfinite(eps) || eps < 1.1754944e-38)
-        return fail(DMAS_ERR_INVALID_ARG, "cf_eps must be a positive normal FP32 value");
-    const int L = d->fir_len == 0 ? 63 : d->fir_len;
-    if (L < 1 || L > DMAS_MAX_FIR_LEN || (L % 2) == 0)
-        return fail(DMAS_ERR_INVALID_ARG, "fir_len %d must be odd in 1..%d", L, DMAS_MAX_FIR_LEN);
-    const double fc = d->fir_fc == 0.0 ? 5000.0 : d->fir_fc;
-    if (!d->fir_taps && !(fc > 0.0 && fc < 0.5 * d->fs))
-        return fail(DMAS_ERR_INVALID_ARG, "fir_fc must lie in (0, fs/2)");
-    if (!finite_all(d->mic_pos, 3 * (size_t)M) || !finite_all(d->dirs, 3 * (size_t)D))
-        return fail(DMAS_ERR_INVALID_ARG, "geometry contains NaN or Inf");
-    if (d->geometry == DMAS_FARFIELD) {
-        for (int p = 0; p < D; ++p) {
-            const double *u = d->dirs + 3 * p;
-            const double nrm = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            if (std::fabs(nrm - 1.0) > 1e-6)
-                return fail(DMAS_ERR_INVALID_ARG, "far-field direction %d is not a unit vector (|u| = %.9g)", p, nrm);
-        }
-    }
-    {
-        // Steering delays are whole samples in 32-bit integers: keep |fs*tau| far from overflow.
-        double rmax = 0, vmax = 0;
-        for (int i = 0; i < M; ++i)
-            rmax = std::max(rmax, std::sqrt(d->mic_pos[3 * i] * d->mic_pos[3 * i] + d->mic_pos[3 * i + 1] * d->mic_pos[3 * i + 1] +
-                                            d->mic_pos[3 * i + 2] * d->mic_pos[3 * i + 2]));
-        if (d->geometry == DMAS_NEARFIELD)
-            for (int q = 0; q < D; ++q)
-                vmax = std::max(vmax, std::sqrt(d->dirs[3 * q] * d->dirs[3 * q] + d->dirs[3 * q + 1] * d->dirs[3 * q + 1] +
-                                                d->dirs[3 * q + 2] * d->dirs[3 * q + 2]));
-        const double span = d->fs * (d->geometry == DMAS_NEARFIELD ? 2.0 * (rmax + vmax) : rmax) / c;
-        if (!(span < 1.0e8))
-            return fail(DMAS_ERR_INVALID_ARG, "geometry spans %.3g samples of delay; at most 1e8 is supported", span);
-    }
-    if (d->compensated && (d->geometry != DMAS_FARFIELD || !d->use_cf))
-        return fail(DMAS_ERR_UNSUPPORTED, "Kahan and FP64 accumulation are built for far field with CF only");
-    if (d->delay_mode == DMAS_DELAY_LINEAR && !d->use_cf)
-        return fail(DMAS_ERR_UNSUPPORTED, "linear delays are built with CF only");
-    if (d->delay_mode == DMAS_DELAY_LINEAR && d->compensated)
-        return fail(DMAS_ERR_UNSUPPORTED, "linear delays are built with FP32 accumulation only");
-    const int decim = d->env_decimation == 0 ? 1 : d->env_decimation;
-    if (decim < 1 || decim > T) return fail(DMAS_ERR_INVALID_ARG, "env_decimation %d must lie in 1..T", decim);
-    if (d->mf_len < 0 || d->mf_len > DMAS_MAX_MF_LEN || (d->mf_pulse && d->mf_len < 1) || (!d->mf_pulse && d->mf_len))
-        return fail(DMAS_ERR_INVALID_ARG, "mf_len must be 1..%d with mf_pulse, 0 without", DMAS_MAX_MF_LEN);
-    if (d->mf_pulse) {
-        for (int k = 0; k < d->mf_len; ++k)
-            if (!std::isfinite(d->mf_pulse[k])) return fail(DMAS_ERR_INVALID_ARG, "mf_pulse contains NaN or Inf");
-    }
-    if (d->fir_taps) {
-        for (int k = 0; k < L; ++k)
-            if (!std::isfinite(d->fir_taps[k])) return fail(DMAS_ERR_INVALID_ARG, "fir_taps contain NaN or Inf");
-    }
+    const double c = vals.c, eps = vals.cf_eps, fc = vals.fir_fc;
+    const int L = vals.fir_len, decim = vals.env_decimation;
 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -809,6 +738,12 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         }
     }
 
+    p->device_bytes = sizeof(double) * 3 * ((size_t)M + (size_t)D) + sizeof(int32_t) * tiles.size() +
+                      sizeof(float) * taps.size() + sizeof(float) * (size_t)p->mf_len +
+                      (p->d_tile_off ? sizeof(int32_t) * ((size_t)p->num_tiles * W * M + dmas::kLaneBlockMax +
+                                                          (size_t)p->num_tiles * M)
+                                     : 0);
+
     const char *fixed_seg = std::getenv("DMAS_SEGMENT");
     const int seg_override = fixed_seg ? std::atoi(fixed_seg) : 0;
     p->nseg_rf = p->nseg_env = 1;   // dmas::shape_of() needs a grid; the occupancy query ignores it
@@ -866,6 +801,7 @@ dmas_status_t dmas_plan_query(dmas_plan_t p, dmas_plan_info_t *info)
     info->fir_len = p->fir_len;
     info->workgroups = (int64_t)p->num_tiles * p->nseg_env;
     info->delay_table_bytes = p->d_tile_off ? (int64_t)p->num_tiles * p->M * (dmas::kDirsPerTile + 1) * 4 : 0;
+    info->device_bytes = (int64_t)p->device_bytes;
     return DMAS_OK;
 }
 
