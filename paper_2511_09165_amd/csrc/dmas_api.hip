@@ -638,14 +638,22 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         for (int v : spread) p->halo = std::max(p->halo, v);
     }
     // ---- LDS layout: mic_block x row windows, reference delays, envelope rings ----
+    // Per-tile delay tables for whole-sample delays, when of modest size (the
+    // delay mode selects the kernel, so it is fixed before the LDS layout and
+    // the occupancy queries below).
+    const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
+    p->tables = !p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE");
+    // with more microphones than lanes the kernel reads a block's offsets as one
+    // scalar block of lane_block_max(n) entries: that caps the block
+    const bool lane_tables = dmas::shape_of(p, true).delay == dmas::kDelayTableLanes;
     const int C = dmas::kChunk;
     const int H = (L - 1) / 2;
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
     p->row = (p->row + 3) & ~3;
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
-    // envelope: taps, then per-wave rings, or with more microphones than lanes
+    // envelope: taps, then per-wave rings, or with per-block delay tables
     // per-wave carries while the rings share the window region
-    const bool share = dmas::rings_share_windows(M);
+    const bool share = dmas::rings_share_windows(dmas::shape_of(p, true).delay);
     const size_t ring_bytes = sizeof(float) * (size_t)W * dmas::ring_stride(H);
     const size_t env_side = sizeof(float) * (size_t)(dmas::env_taps_len(H) +
                                                      W * (share ? dmas::carry_stride(H) : dmas::ring_stride(H)));
@@ -660,14 +668,6 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         const size_t win = elem * (size_t)m * p->row;
         return fixed + (env ? (share ? std::max(win, ring_bytes) : win) + env_side : win);
     };
-    // Per-tile delay tables for whole-sample delays, when of modest size (the
-    // delay mode selects the kernel, so it is fixed before the occupancy
-    // queries below).
-    const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
-    p->tables = !p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE");
-    // with more microphones than lanes the kernel reads a block's offsets as one
-    // scalar block of lane_block_max(n) entries: that caps the block
-    const bool lane_tables = dmas::shape_of(p, true).delay == dmas::kDelayTableLanes;
     const int mb_cap = lane_tables ? dmas::lane_block_max(n) : dmas::kMaxMicBlock;
     // Microphones per LDS block, from the envelope kernel's occupancy (its
     // registers, LDS and the wave limit decide): with M <= 64 the largest

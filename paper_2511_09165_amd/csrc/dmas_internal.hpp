@@ -92,9 +92,10 @@ __host__ __device__ constexpr int env_prefix(int H) { return H + env_lead(H); }
 // Envelope LDS of a workgroup: after the channel windows come the reference
 // delays (kMaxMicBlock ints), a taps table of env_taps_len(H) floats (kTapLead
 // zeros, the L = 2H + 1 taps in reverse order, zeros) and one ring per wave of
-// ring_stride(H) floats. With more microphones than lanes (many blocks per
-// chunk, where LDS decides the block size) the rings instead share the window
-// region, which they need only in the epilogue after the chunk's last block:
+// ring_stride(H) floats. With per-block delay tables (more microphones than
+// lanes: many blocks per chunk, where LDS decides the block size) the rings
+// instead share the window region, which they need only in the epilogue after
+// the chunk's last block:
 // the region then holds max(windows, kDirsPerTile rings), and per wave
 // carry_stride(H) floats after the taps keep the env_prefix(H) values of |y|
 // carried from one chunk to the next while the windows occupy the region. A
@@ -111,8 +112,9 @@ __host__ __device__ constexpr int ring_logical(int H)
 }
 __host__ __device__ constexpr int ring_stride(int H) { return (ring_logical(H) + ring_logical(H) / 16 + 1 + 3) & ~3; }
 __host__ __device__ constexpr int carry_stride(int H) { return (env_prefix(H) + 3) & ~3; }
-// Whether the envelope rings share the window region (M microphones).
-__host__ __device__ constexpr bool rings_share_windows(int M) { return M > kWaveSize; }
+// Whether the envelope rings share the window region: a property of the delay
+// mode, so that the other kernels carry none of its address arithmetic.
+__host__ __device__ constexpr bool rings_share_windows(int delay) { return delay == kDelayTableLanes; }
 // Floats of the window region: mic_block rows of `row` elements of elem_floats
 // floats, or the rings if they share it and need more.
 __host__ __device__ constexpr int window_region_floats(int mic_block, int row, int elem_floats, bool env, int H,

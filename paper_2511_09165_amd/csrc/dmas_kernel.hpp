@@ -508,7 +508,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     // LDS: the window region (mic_block x row windows; with `share` also the
     // per-wave rings in the envelope epilogue), reference delays, taps table,
     // then per wave either its ring or (share) the |y| it carries between chunks
-    const bool share = ENV && rings_share_windows(p.M);
+    constexpr bool share = ENV && rings_share_windows(DM);
     const int region = window_region_floats(p.mic_block, p.row, ROOTS ? 2 : 1, ENV, H, share);
     Elem *xwin = reinterpret_cast<Elem *>(smem);                             // mic_block x row
     int *dref_lds = reinterpret_cast<int *>(smem + region);                  // kMaxMicBlock
@@ -633,7 +633,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 
     if (all_mics) block_geometry(0);
     if constexpr (ENV) {
-        if (share) {
+        if constexpr (share) {
             for (int i = lane; i < carry_stride(H); i += kWaveSize) carry[i] = 0.0f;
         } else {
             for (int i = lane; i < ring_stride(H); i += kWaveSize) ring[i] = 0.0f;
@@ -744,18 +744,23 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const float out_scale = fp32_out_scale<N>(p);
 
     // Power sums. Plain FP32 sums (PEEL): each chunk's first microphone starts
-    // them, and they are cleared once here so that envelope-only passes (no
-    // microphones) read defined values. Other sums: cleared here and after
-    // each epilogue.
+    // them, so they are the pass's own (nothing carried from one pass to the
+    // next: sums kept live across the envelope's matrix-core steps cost 9-14
+    // VGPRs and a workgroup per CU on some kernels) and envelope-only passes
+    // do not read them. Other sums: cleared here and after each epilogue.
     constexpr bool PEEL = ACC == kAccF32;
-    Acc<N, CF, ACC> acc[K];
+    Acc<N, CF, ACC> acc_kept[K];
+    if constexpr (!PEEL) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) acc[j].zero();
+        for (int j = 0; j < K; ++j) acc_kept[j].zero();
+    }
     for (int ch = 0; ch < npasses; ++ch) {
         const int tc = ystart + ch * C;
         // Passes after the last computed chunk are envelope-only: their samples
         // lie past T (zero) or feed only outputs past g1, and enter the ring as zeros.
         const bool compute = ch < nchunks;
+        Acc<N, CF, ACC> acc_pass[K];
+        auto &acc = *(PEEL ? &acc_pass : &acc_kept);
 
         for (int blk = 0; blk < (compute ? nblocks : 0); ++blk) {
             if (!all_mics) block_geometry(blk);
@@ -863,11 +868,12 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 
         // rings in the window region: every wave (active or not) has read its
         // last window before any ring is written
-        if (share) __syncthreads();
+        if constexpr (share) __syncthreads();
         if (!active) continue;
         // ---- epilogue: Newton-Girard, CF, store or envelope ----
         const size_t orow = (size_t)dir * (size_t)p.out_T;
         if constexpr (!ENV) {
+            // (every pass computes: without the envelope there are no envelope-only passes)
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int t = tc + lane + kWaveSize * j;
@@ -879,7 +885,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             // ring: the carried prefix, |y| of samples [tc, tc + C), zeros after
             // them. Samples at or past T (and every sample of an envelope-only
             // pass) enter as zeros; tc >= 0, so lane + 64 j < lim is the whole test.
-            if (share) {
+            if constexpr (share) {
                 for (int i = lane; i < env_prefix(H); i += kWaveSize) ring[i + (i >> 4)] = carry[i];
                 for (int i = env_prefix(H) + C + lane; i < ring_logical(H); i += kWaveSize)
                     ring[i + (i >> 4)] = 0.0f;
@@ -887,7 +893,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             const int lim = compute ? p.T - tc : 0;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const float y = finish_pixel<N, CF, ACC>(acc[j], p, out_scale);
+                const float y = !PEEL || compute ? finish_pixel<N, CF, ACC>(acc[j], p, out_scale) : 0.0f;
                 if constexpr (!PEEL) acc[j].zero();
                 const int ri = env_prefix(H) + lane + kWaveSize * j;
                 ring[ri + (ri >> 4)] = lane < lim - kWaveSize * j ? __builtin_fabsf(y) : 0.0f;
@@ -915,12 +921,15 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //    (83 and 95 VGPRs unconstrained) and Kahan / FP64 sums up to order 5 with
 //    scalar-cache tables (87-89). The cap spills 16-56 bytes per lane, which
 //    costs less than the third workgroup gains: 9-17 % faster on the
-//    32-microphone frame, 10 % on the near-field frame at order 7.
+//    32-microphone frame, 10 % on the near-field frame at order 7. Also
+//    delays computed on the device (whole-sample or linear) with FP32 sums:
+//    the envelope kernels at orders 4 and 5 need 82-85 VGPRs unconstrained
+//    and fit the cap with no spill (8 bytes for near-field linear delays).
 //  * none otherwise: Kahan / FP64 sums at orders 6-8 spill 90-280 bytes under
 //    the cap and ran 1.2-6x slower.
 template <int N, int ACC, int DM>
 constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableLanes)     ? 8
-                                 : ACC == kAccF32 ? (N >= 6 ? 6 : 1)
+                                 : ACC == kAccF32 ? (N >= 6 || DM == kDelayLinear || DM == kDelayComputed ? 6 : 1)
                                  : (N <= 5 && DM == kDelayTable) ? 6 : 1;
 
 template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
