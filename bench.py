@@ -331,7 +331,8 @@ def bench_nearfield(args) -> dict:
         x = torch.from_numpy(frame.x_f32()).cuda()
         out = torch.empty((D, T), dtype=torch.float32, device="cuda")
         steps = max(3, args.steps // 10)
-        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, max(2, args.warmup // 20),
+        warmup = max(2, args.warmup // 20)
+        ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, warmup,
                                         torch.cuda.current_stream())
         info = plan.info()
     pixels = D * T
@@ -341,6 +342,7 @@ def bench_nearfield(args) -> dict:
         "fir_len": fir_len})
     rec["metric"] = "direction*samples/sec, order-3 DMAS+CF, 1024 mics, near field"
     rec["steps"] = steps
+    rec["warmup"] = warmup
     rec["roofline"] = _roofline(launch_slots(M, T, D, n, True), pixels, kernel_ms, fir=fir_flops(D, T, fir_len))
     rec["extra"] = {"plan": info}
     return rec
@@ -368,6 +370,7 @@ def bench_linear(args) -> dict:
         out = torch.empty((D, T), dtype=torch.float32, device="cuda")
         stream = torch.cuda.current_stream()
         steps = max(5, args.steps // 5)
+        settle = _settle(lambda: plan.envelope(x, out=out), stream)
         ms_per_step, kernel_ms = _timed(lambda: plan.envelope(x, out=out), steps, args.warmup, stream)
         info = plan.info()
     pixels = D * T
@@ -377,6 +380,7 @@ def bench_linear(args) -> dict:
         "M": M, "D": D, "T": T, "order": n, "cf": True, "fir_len": fir_len, "delays": "linear"})
     rec["metric"] = "direction*samples/sec, order-5 DMAS+CF, 32 mics, linear fractional delays"
     rec["steps"] = steps
+    rec["clock_settle"] = {"launches": settle, "ms": 250}
     rec["roofline"] = _roofline(D * T * linear_pixel_slots(M, n, True), pixels, kernel_ms,
                                 fir=fir_flops(D, T, fir_len))
     rec["extra"] = {"plan": info}
@@ -407,6 +411,7 @@ def bench_pipeline(args) -> dict:
             plan.envelope(x, out=out)
 
         steps = max(5, args.steps // 5)
+        settle = _settle(step, stream)
         ms_per_step, step_ms = _timed(step, steps, args.warmup, stream)
         mf_ms = _timed(lambda: plan.matched_filter(raw, out=x), steps, 2, stream)[1]
         env_ms = _timed(lambda: plan.envelope(x, out=out), steps, 2, stream)[1]
@@ -420,6 +425,7 @@ def bench_pipeline(args) -> dict:
         "mf_len": P})
     rec["metric"] = "direction*samples/sec, raw -> matched filter -> order-5 DMAS+CF -> decimated envelope"
     rec["steps"] = steps
+    rec["clock_settle"] = {"launches": settle, "ms": 250}
     # the FIR runs at full rate (every sample) on the matrix cores; the algorithmic count keeps
     # only the stored outputs
     rec["roofline"] = _roofline(env_slots, pixels, env_ms, fir=fir_flops(D, -(-T // decim), fir_len))
@@ -568,7 +574,7 @@ def serving_summary(args) -> dict:
             r = _serve_trace(mode, plans, xs, pix, gaps, picks, rate)
             res[mode] = {k: r[k] for k in ("p50_ms", "p99_ms", "max_ms", "achieved_frames_per_s",
                                            "direction_samples_per_s", "frames", "failed", "launches",
-                                           "mean_frames_per_launch")}
+                                           "mean_frames_per_launch", "client_late_max_ms", "busy_retries")}
     finally:
         for p in plans:
             p.close()
@@ -624,7 +630,7 @@ def main(argv=None) -> int:
                          "-> matched filter -> DMAS+CF -> decimated envelope")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="headline line without its serving leg")
-    ap.add_argument("--serving-summary-s", type=float, default=1.0,
+    ap.add_argument("--serving-summary-s", type=float, default=3.0,
                     help="seconds of 2000 frames/s arrivals in the headline line's serving leg")
     ap.add_argument("--no-delay-modes", action="store_true",
                     help="headline line without the computed-delay timings (plan tables vs eq. (1) on the device)")

@@ -8,8 +8,13 @@ channel data (so storage rounding is part of each form's error):
   env_rel  the same for the envelope
   env_db   max |20 log10(env / env_ref)| over pixels within 80 dB of the peak
            (the dynamic range the paper reports for DMAS5)
+  snr_db   |SNR_img(env) - SNR_img(env_ref)|, image SNR by eq. (18) over the
+           off-target samples (further than the burst length plus the largest
+           steering delay from every reflector's echo)
 Bounds: FP32 storage within the 1e-4 parity tolerance; FP16 within 2e-3 and
-BF16 within 1.6e-2 (a few units of their roundoff 2^-11 and 2^-8).
+BF16 within 1.6e-2 (a few units of their roundoff 2^-11 and 2^-8). The image
+SNR is a mean over off-target pixels, so its deviation is at most the largest
+dB deviation among them: it takes the env_db bound.
 If DMAS_REPORT_DIR is set, the table is also written there as JSON.
 """
 
@@ -46,6 +51,23 @@ def _db_dev(env, ref, floor_db=-80.0):
     return float(np.abs(20 * np.log10(np.maximum(env[m], 1e-300) / ref[m])).max())
 
 
+def _off_target(frame):
+    """Samples further than the burst length plus the largest steering delay from every echo."""
+    d = np.abs(oracle.delays(frame.mic_pos, frame.dirs, frame.fs, frame.c)).max()
+    guard = frame.truth["pulse_len"] + d
+    t = np.arange(frame.num_samples)
+    far = np.ones(frame.num_samples, dtype=bool)
+    for r in frame.truth["reflectors"]:
+        far &= np.abs(t - r["onset"]) > guard
+    return far
+
+
+def _image_snr(env, far):
+    """Eq. (18): 20 log10(1 / mean of the off-target pixels) of the image normalised to a maximum of 1."""
+    img = env / env.max()
+    return float(20 * np.log10(1.0 / img[:, far].mean()))
+
+
 def test_precision_sweep():
     from paper_2511_09165_amd import plan_for_frame
     table = []
@@ -54,6 +76,9 @@ def test_precision_sweep():
         taps = oracle.lowpass_taps(63, 5000.0, f.fs)
         y_ref = oracle.frame_rows(f)                      # original FP64 data
         env_ref = oracle.envelope(y_ref, taps.astype(np.float32).astype(np.float64))
+        far = _off_target(f)
+        assert far.sum() >= 64, "too few off-target samples"
+        snr_ref = _image_snr(env_ref, far)
         for dt in ("f32", "f16", "bf16"):
             xq, scale = _quantise(f.x, dt)
             xq = xq.cuda()
@@ -66,11 +91,13 @@ def test_precision_sweep():
                 row = {"order": n, "storage": dt, "accumulate": acc, "ng_fp64": ng64,
                        "rf_rel": float(np.abs(y - y_ref).max() / np.abs(y_ref).max()),
                        "env_rel": float(np.abs(env - env_ref).max() / env_ref.max()),
-                       "env_db": _db_dev(env, env_ref)}
+                       "env_db": _db_dev(env, env_ref),
+                       "snr_img_ref": snr_ref, "snr_db": abs(_image_snr(env, far) - snr_ref)}
                 table.append(row)
     for r in table:
         print(f"n={r['order']} {r['storage']:>4} acc={r['accumulate']:>5} ng64={int(r['ng_fp64'])}: "
-              f"rf {r['rf_rel']:.2e} env {r['env_rel']:.2e} dB(-80) {r['env_db']:.2e}", flush=True)
+              f"rf {r['rf_rel']:.2e} env {r['env_rel']:.2e} dB(-80) {r['env_db']:.2e} "
+              f"SNR_img {r['snr_img_ref']:.1f} dB dev {r['snr_db']:.2e}", flush=True)
     out_dir = os.environ.get("DMAS_REPORT_DIR")
     if out_dir:
         os.makedirs(out_dir, exist_ok=True)
@@ -80,3 +107,4 @@ def test_precision_sweep():
         assert r["rf_rel"] <= BOUND[r["storage"]], r
         assert r["env_rel"] <= BOUND[r["storage"]], r
         assert r["env_db"] <= DB_BOUND[r["storage"]], r
+        assert r["snr_db"] <= DB_BOUND[r["storage"]], r
