@@ -243,8 +243,11 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  *   - a scheduler thread admits queued frames in arrival order while their
  *     device input, root plane (M*T*8 bytes, plans with whole-sample delays
  *     and n >= 2) and output fit in the HBM budget (an arena allocated once;
- *     the plan's own device memory is counted there too while any frame of
- *     the plan holds device memory),
+ *     while any frame of a plan holds device memory, an arena range of the
+ *     plan's own device memory is reserved too, as accounting only: the
+ *     plan's memory was allocated by dmas_plan_create, so the device holds
+ *     the arena plus the plans, and the budget bounds the frames' memory
+ *     together with that of the plans in use),
  *     copies the input and fills the root plane on a copy stream, and groups
  *     admitted frames into one
  *     multi-frame launch (frames with the same CF / envelope / geometry flags,
@@ -277,7 +280,8 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
 typedef struct dmas_server_s *dmas_server_t;
 
 typedef struct {
-    int64_t hbm_budget_bytes;  /* device memory for admitted frames' inputs, root planes and outputs (> 0) */
+    int64_t hbm_budget_bytes;  /* arena for admitted frames' inputs, root planes and outputs, which
+                                  also counts the device memory of the plans in use (> 0) */
     int64_t staging_bytes;     /* pinned host memory for queued inputs; 0 selects 256 MiB */
     int32_t num_streams;       /* launches in flight at once; 0 selects 2 */
     int32_t max_batch_frames;  /* frames per launch; 0 selects 64; 1 = one plain launch per frame */
