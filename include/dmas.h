@@ -158,7 +158,10 @@ dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *desc);
  * DMAS_SEGMENT=s fixes the samples per workgroup (rounded up to 32),
  * DMAS_MIC_BLOCK=m the microphones per LDS block (clamped to the valid
  * range), DMAS_NO_DELAY_TABLE evaluates the delays on the device instead of
- * building tables, DMAS_LOG prints the plan's choices and errors to stderr. */
+ * building tables, DMAS_BLOCK_TABLES=0/1 chooses how a kernel with at most
+ * 64 microphones reads the tables (one microphone ahead, or a block of
+ * offsets at a time), DMAS_LOG prints the plan's choices and errors to
+ * stderr. */
 dmas_status_t dmas_plan_create(const dmas_plan_desc_t *desc, dmas_plan_t *out);
 
 /* Release a plan and its device memory. NULL is a no-op. Work queued with

@@ -643,9 +643,21 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // the occupancy queries below).
     const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
     p->tables = !p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE");
-    // with more microphones than lanes the kernel reads a block's offsets as one
-    // scalar block of lane_block_max(n) entries: that caps the block
-    const bool lane_tables = dmas::shape_of(p, true).delay == dmas::kDelayTableLanes;
+    // Per-block tables (each wave reads its block's offsets and reference
+    // delays as scalars before the block's barrier, and the envelope rings
+    // share the window region): always with more microphones than lanes; with
+    // fewer, for plain FP32 sums up to order 7, where they measured 1-3 %
+    // faster on the 32-microphone frame and 1.5-11 % on serving frames of
+    // 16-64 microphones (bitwise identical). At order 8 and with Kahan or
+    // FP64 sums, whose register budgets differ, the per-microphone reads one
+    // ahead stay (3-6 % faster there). DMAS_BLOCK_TABLES=0/1 overrides the
+    // choice for M <= 64 (tuning).
+    p->block_tables = M > dmas::kWaveSize || (p->compensated == DMAS_ACCUM_F32 && n <= 7);
+    if (const char *bt = std::getenv("DMAS_BLOCK_TABLES"))
+        p->block_tables = M > dmas::kWaveSize || std::atoi(bt) != 0;
+    // the kernel then reads a block's offsets as one scalar block of
+    // table_block_max(n) entries: that caps the block
+    const bool block_tables_mode = dmas::shape_of(p, true).delay == dmas::kDelayTableBlocks;
     const int C = dmas::kChunk;
     const int H = (L - 1) / 2;
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
@@ -668,7 +680,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
         const size_t win = elem * (size_t)m * p->row;
         return fixed + (env ? (share ? std::max(win, ring_bytes) : win) + env_side : win);
     };
-    const int mb_cap = lane_tables ? dmas::lane_block_max(n) : dmas::kMaxMicBlock;
+    const int mb_cap = block_tables_mode ? dmas::table_block_max(n) : dmas::kMaxMicBlock;
     // Microphones per LDS block, from the envelope kernel's occupancy (its
     // registers, LDS and the wave limit decide): with M <= 64 the largest
     // block that keeps three workgroups per CU (or as many as any block
@@ -720,9 +732,9 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // results between lanes.
     if (p->tables) {
         const size_t n_off = (size_t)p->num_tiles * W * M, n_dref = (size_t)p->num_tiles * M;
-        // kLaneBlockMax spare entries: a scalar block read may run past the last row
-        e = hipMalloc((void **)&p->d_tile_off, sizeof(int32_t) * (n_off + dmas::kLaneBlockMax));
-        if (e == hipSuccess) e = hipMemset(p->d_tile_off + n_off, 0, sizeof(int32_t) * dmas::kLaneBlockMax);
+        // kTableBlockMax spare entries: a scalar block read may run past the last row
+        e = hipMalloc((void **)&p->d_tile_off, sizeof(int32_t) * (n_off + dmas::kTableBlockMax));
+        if (e == hipSuccess) e = hipMemset(p->d_tile_off + n_off, 0, sizeof(int32_t) * dmas::kTableBlockMax);
         if (e == hipSuccess) e = hipMalloc((void **)&p->d_tile_dref, sizeof(int32_t) * n_dref);
         if (e == hipSuccess) {
             auto kern = p->nearfield ? tile_table_kernel<true> : tile_table_kernel<false>;
@@ -740,7 +752,7 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
 
     p->device_bytes = sizeof(double) * 3 * ((size_t)M + (size_t)D) + sizeof(int32_t) * tiles.size() +
                       sizeof(float) * taps.size() + sizeof(float) * (size_t)p->mf_len +
-                      (p->d_tile_off ? sizeof(int32_t) * ((size_t)p->num_tiles * W * M + dmas::kLaneBlockMax +
+                      (p->d_tile_off ? sizeof(int32_t) * ((size_t)p->num_tiles * W * M + dmas::kTableBlockMax +
                                                           (size_t)p->num_tiles * M)
                                      : 0);
 

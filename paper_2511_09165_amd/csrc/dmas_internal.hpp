@@ -11,11 +11,11 @@ namespace dmas {
 constexpr int kWaveSize = 64;
 constexpr int kMaxOrder = 8;
 constexpr int kMaxMicBlock = 64;   // microphones staged in LDS at once (<= wave size)
-// Microphones per block with kDelayTableLanes (a block's offsets are read as
+// Microphones per block with kDelayTableBlocks (a block's offsets are read as
 // one scalar block into SGPRs): 16 for every order (the order-3 kernels, which
 // run eight waves per SIMD, hold them within their SGPR budget).
-__host__ __device__ constexpr int lane_block_max(int) { return 16; }
-constexpr int kLaneBlockMax = 16;  // the largest, for padding the tables
+__host__ __device__ constexpr int table_block_max(int) { return 16; }
+constexpr int kTableBlockMax = 16;  // the largest, for padding the tables
 
 // Everything a beamforming launch needs, passed by value as the kernel argument.
 struct KernelParams {
@@ -68,12 +68,15 @@ struct LaunchShape {
 
 // How a kernel obtains its steering delays: evaluated on the device (whole
 // samples), evaluated with linear interpolation, or from the plan's per-tile
-// tables (whole samples). With at most 64 microphones the hot loop reads each
-// microphone's offset through the scalar cache one ahead of use; with more
-// (kDelayTableLanes) each wave reads its block's offsets as one scalar block
-// before the block's barrier and the reference delays per lane (per-microphone
-// scalar reads of a large table left their latency in the hot loop).
-enum : int { kDelayComputed = 0, kDelayLinear = 1, kDelayTable = 2, kDelayTableLanes = 3 };
+// tables (whole samples). With kDelayTable the hot loop reads each
+// microphone's offset through the scalar cache one ahead of use; with
+// kDelayTableBlocks each wave reads its block's offsets and the reference
+// delays of the rows it stages as scalars before the block's barrier, and the
+// block's microphone loop is straight-line code (per-microphone scalar reads
+// of a large table left their latency in the hot loop). The plan picks the
+// block form for more than 64 microphones and for plain FP32 sums up to
+// order 7.
+enum : int { kDelayComputed = 0, kDelayLinear = 1, kDelayTable = 2, kDelayTableBlocks = 3 };
 
 // Compile-time tiling shared by host and device: waves (= directions) per
 // workgroup and output samples per lane per chunk.
@@ -114,7 +117,7 @@ __host__ __device__ constexpr int ring_stride(int H) { return (ring_logical(H) +
 __host__ __device__ constexpr int carry_stride(int H) { return (env_prefix(H) + 3) & ~3; }
 // Whether the envelope rings share the window region: a property of the delay
 // mode, so that the other kernels carry none of its address arithmetic.
-__host__ __device__ constexpr bool rings_share_windows(int delay) { return delay == kDelayTableLanes; }
+__host__ __device__ constexpr bool rings_share_windows(int delay) { return delay == kDelayTableBlocks; }
 // Floats of the window region: mic_block rows of `row` elements of elem_floats
 // floats, or the rings if they share it and need more.
 __host__ __device__ constexpr int window_region_floats(int mic_block, int row, int elem_floats, bool env, int H,
@@ -136,7 +139,7 @@ __host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; 
 
 // Batched launch over frames of order n with the given CF / envelope /
 // geometry flags and whole-sample delay mode (kDelayComputed, kDelayTable or
-// kDelayTableLanes, the same for all frames; plain sums); grid = total
+// kDelayTableBlocks, the same for all frames; plain sums); grid = total
 // workgroups.
 hipError_t launch_batch(int order, const BatchParams &bp, bool cf, bool env, bool nearfield, int delay,
                         unsigned grid, size_t lds_bytes, hipStream_t stream);

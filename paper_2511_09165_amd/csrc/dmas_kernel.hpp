@@ -493,7 +493,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 {
     constexpr bool LINEAR = DM == kDelayLinear;
     constexpr bool TAB = DM == kDelayTable;          // tables through the scalar cache
-    constexpr bool TAB_LANES = DM == kDelayTableLanes; // offsets per block, references per lane
+    constexpr bool TAB_BLOCKS = DM == kDelayTableBlocks; // offsets and references per block, as scalars
     constexpr int W = kDirsPerTile;
     constexpr int K = kSamplesPerLane;
     constexpr int C = kChunk;
@@ -544,11 +544,10 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     //    direction, microphone) and reference delays per (tile, microphone),
     //    read through the scalar cache (constant address space: the tables
     //    do not change while a kernel runs), so the per-microphone LDS
-    //    address of the hot loop costs one vector add. With M <= 64 the hot
-    //    loop reads each offset one microphone ahead; with more microphones
-    //    (TAB_LANES) a wave reads its block's offsets as one scalar block
-    //    before the block's barrier and each lane its microphone's reference
-    //    delay;
+    //    address of the hot loop costs one vector add. Either the hot loop
+    //    reads each offset one microphone ahead (TAB), or (TAB_BLOCKS) a wave
+    //    reads its block's offsets as one scalar block before the block's
+    //    barrier, and the reference delays of the rows it stages;
     //  * M <= 64 without tables (linear delays): lane i of every wave computes
     //    its direction's delay for microphone i once, and wave 0 (the tile's
     //    reference direction) publishes its delays in LDS for the staging step;
@@ -557,22 +556,22 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     // Without tables, after a barrier each lane turns (delay - reference
     // delay) into its LDS offset.
     typedef const __attribute__((address_space(4))) int32_t const_i32;
-    constexpr bool table = TAB;   // p.tile_off and p.tile_dref are set (also with TAB_LANES)
-    const bool all_mics = !table && !TAB_LANES && p.M <= kWaveSize;
+    constexpr bool table = TAB;   // p.tile_off and p.tile_dref are set (also with TAB_BLOCKS)
+    const bool all_mics = !table && !TAB_BLOCKS && p.M <= kWaveSize;
     const_i32 *off_row = table ? reinterpret_cast<const_i32 *>(
                                      reinterpret_cast<uintptr_t>(p.tile_off + ((size_t)tile * W + wave) * p.M))
                                : nullptr;
-    const_i32 *dref_row = (table || TAB_LANES) ? reinterpret_cast<const_i32 *>(
+    const_i32 *dref_row = (table || TAB_BLOCKS) ? reinterpret_cast<const_i32 *>(
                                                      reinterpret_cast<uintptr_t>(p.tile_dref + (size_t)tile * p.M))
                                                : nullptr;
-    const int32_t *off_lanes = TAB_LANES ? p.tile_off + ((size_t)tile * W + wave) * p.M : nullptr;
-    // tables for more than 64 microphones: the block's window offsets of this wave's direction,
+    const int32_t *off_lanes = TAB_BLOCKS ? p.tile_off + ((size_t)tile * W + wave) * p.M : nullptr;
+    // per-block tables: the block's window offsets of this wave's direction,
     // loaded as one scalar block before the block's barrier (mic_block <= 16;
     // the table is padded so that the 16-entry read stays inside it)
-    const_i32 *off_srow = TAB_LANES ? reinterpret_cast<const_i32 *>(reinterpret_cast<uintptr_t>(off_lanes)) : nullptr;
-    constexpr int LB = lane_block_max(N);
+    const_i32 *off_srow = TAB_BLOCKS ? reinterpret_cast<const_i32 *>(reinterpret_cast<uintptr_t>(off_lanes)) : nullptr;
+    constexpr int LB = table_block_max(N);
     int soff[LB];
-    // TAB_LANES: reference delays of the (at most two: mic_block <= 2 W) rows
+    // TAB_BLOCKS: reference delays of the (at most two: mic_block <= 2 W) rows
     // this wave stages, wave and wave + W of the block
     int sdref0 = 0, sdref1 = 0;
     int mydw = 0;
@@ -582,7 +581,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     auto block_geometry = [&](int blk) {
         if (table) return;
         const int mic = blk * p.mic_block + lane;
-        if constexpr (TAB_LANES) {
+        if constexpr (TAB_BLOCKS) {
             // scalar loads issued before the block's barrier so they overlap the wait
             const_i32 *ob = off_srow + blk * p.mic_block;
 #pragma unroll
@@ -604,11 +603,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     };
     // Reference delay of microphone i (wave-uniform) of block blk, for staging.
     auto dref_of = [&](int blk, int i) {
-        if constexpr (TAB_LANES) return i == wave ? sdref0 : sdref1;
+        if constexpr (TAB_BLOCKS) return i == wave ? sdref0 : sdref1;
         return table ? dref_row[blk * p.mic_block + i] : dref_lds[all_mics ? blk * p.mic_block + i : i];
     };
     auto block_offsets = [&](int blk) {
-        if (table || TAB_LANES) return;
+        if (table || TAB_BLOCKS) return;
         const int mic = blk * p.mic_block + lane;
         int dw = mydw;
         float fr = myfrac;
@@ -770,7 +769,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             // With many small blocks (more than 64 microphones) the waves issue
             // their window loads at raised priority, so the loads go out early
             // (0.9 % on the 1024-microphone frame; 0.4 % slower with 32).
-            if constexpr (TAB_LANES) __builtin_amdgcn_s_setprio(2);
+            const bool prio_staging = TAB_BLOCKS && p.M > kWaveSize;
+            if (prio_staging) __builtin_amdgcn_s_setprio(2);
             for (int i = wave; i < p.mic_block; i += W) {
                 const int mic = blk * p.mic_block + i;
                 Elem *dst = xwin + i * p.row;
@@ -788,7 +788,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                     for (int r = lane; r < p.row; r += kWaveSize) dst[r] = Elem{};
                 }
             }
-            if constexpr (TAB_LANES) __builtin_amdgcn_s_setprio(0);
+            if (prio_staging) __builtin_amdgcn_s_setprio(0);
             __syncthreads();
             // ---- hot loop: delayed samples -> roots -> power sums ----
             if (active) {
@@ -849,7 +849,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                     } else {
                         for (int i = 0; i < nm; ++i) rest(i);
                     }
-                } else if constexpr (TAB_LANES) {
+                } else if constexpr (TAB_BLOCKS) {
                     if (PEEL && blk == 0) mic_step(first_t{}, 0, soff[0]);
                     else mic_step(rest_t{}, 0, soff[0]);
 #pragma unroll
@@ -928,7 +928,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //  * none otherwise: Kahan / FP64 sums at orders 6-8 spill 90-280 bytes under
 //    the cap and ran 1.2-6x slower.
 template <int N, int ACC, int DM>
-constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableLanes)     ? 8
+constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableBlocks)     ? 8
                                  : ACC == kAccF32 ? (N >= 6 || DM == kDelayLinear || DM == kDelayComputed ? 6 : 1)
                                  : (N <= 5 && DM == kDelayTable) ? 6 : 1;
 
@@ -1039,7 +1039,7 @@ hipError_t launch_batch_order(const BatchParams &bp, bool cf, bool env, bool nea
                               size_t lds, hipStream_t stream)
 {
     if (table == kDelayTable) return launch_batch_dm<N, kDelayTable>(bp, cf, env, nearfield, grid, lds, stream);
-    if (table == kDelayTableLanes) return launch_batch_dm<N, kDelayTableLanes>(bp, cf, env, nearfield, grid, lds, stream);
+    if (table == kDelayTableBlocks) return launch_batch_dm<N, kDelayTableBlocks>(bp, cf, env, nearfield, grid, lds, stream);
     return launch_batch_dm<N, kDelayComputed>(bp, cf, env, nearfield, grid, lds, stream);
 }
 
@@ -1065,7 +1065,7 @@ hipError_t launch_order(const KernelParams *p, const LaunchShape &s, hipStream_t
     DMAS_CASE(true, false, false, DM, kAccF64)                  \
     DMAS_CASE(true, true, false, DM, kAccF64)
     DMAS_WHOLE(kDelayTable)
-    DMAS_WHOLE(kDelayTableLanes)
+    DMAS_WHOLE(kDelayTableBlocks)
     DMAS_WHOLE(kDelayComputed)
     DMAS_CASE(true, false, false, kDelayLinear, kAccF32)
     DMAS_CASE(true, true, false, kDelayLinear, kAccF32)

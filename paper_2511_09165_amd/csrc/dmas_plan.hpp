@@ -26,6 +26,7 @@ struct dmas_plan_s {
     bool cf = true, nearfield = false, linear = false;
     bool roots = false;    // kernel reads a root plane (whole-sample delays, n >= 2)
     bool tables = false;   // per-tile delay tables (whole-sample delays, <= 2 GiB)
+    bool block_tables = false;   // tables read a block of offsets at a time (kDelayTableBlocks)
     int compensated = 0;   // 0 FP32 sums, 1 Kahan FP32, 2 FP64
     int ng_fp64 = 0;
     int dtype = DMAS_F32;
@@ -111,8 +112,8 @@ inline LaunchShape shape_of(const dmas_plan_s *p, bool env)
     ls.nearfield = p->nearfield;
     ls.delay = p->linear ? kDelayLinear
                : !p->tables ? kDelayComputed
-               : p->M <= kWaveSize ? kDelayTable
-                                   : kDelayTableLanes;
+               : p->block_tables ? kDelayTableBlocks
+                                 : kDelayTable;
     ls.accumulate = p->compensated;
     ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
     ls.lds_bytes = env ? p->lds_env : p->lds_rf;
