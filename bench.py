@@ -98,7 +98,7 @@ def kernel_source_hash() -> str:
     committed HBM counter record applies only while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_09165_amd", "csrc")
-    for name in ("dmas_api.hip", "dmas_internal.hpp", "dmas_kernel.hpp", "dmas_order5.hip"):
+    for name in ("dmas_api.hip", "dmas_internal.hpp", "dmas_kernel.hpp", "dmas_order5.hip", "dmas_plan.hpp"):
         with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update((name + _code_only(f.read())).encode())
     return h.hexdigest()[:16]

@@ -160,8 +160,9 @@ dmas_status_t dmas_plan_desc_init(dmas_plan_desc_t *desc);
  * range), DMAS_NO_DELAY_TABLE evaluates the delays on the device instead of
  * building tables, DMAS_BLOCK_TABLES=0/1 chooses how a kernel with at most
  * 64 microphones reads the tables (one microphone ahead, or a block of
- * offsets at a time), DMAS_LOG prints the plan's choices and errors to
- * stderr. */
+ * offsets at a time), DMAS_RING_SHARING=0/1 whether a kernel reading a block
+ * of offsets at a time keeps the envelope rings in the LDS region of the
+ * channel windows, DMAS_LOG prints the plan's choices and errors to stderr. */
 dmas_status_t dmas_plan_create(const dmas_plan_desc_t *desc, dmas_plan_t *out);
 
 /* Release a plan and its device memory. NULL is a no-op. Work queued with

@@ -644,9 +644,9 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     const size_t table_bytes = (size_t)p->num_tiles * M * (W + 1) * sizeof(int32_t);
     p->tables = !p->linear && table_bytes <= kMaxTileTableBytes && !std::getenv("DMAS_NO_DELAY_TABLE");
     // Per-block tables (each wave reads its block's offsets and reference
-    // delays as scalars before the block's barrier, and the envelope rings
-    // share the window region): always with more microphones than lanes; with
-    // fewer, for plain FP32 sums up to order 7, where they measured 1-3 %
+    // delays as scalars before the block's barrier, and the block's microphone
+    // loop is straight-line code): always with more microphones than lanes;
+    // with fewer, for plain FP32 sums up to order 7, where they measured 1-3 %
     // faster on the 32-microphone frame and 1.5-11 % on serving frames of
     // 16-64 microphones (bitwise identical). At order 8 and with Kahan or
     // FP64 sums, whose register budgets differ, the per-microphone reads one
@@ -655,32 +655,30 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->block_tables = M > dmas::kWaveSize || (p->compensated == DMAS_ACCUM_F32 && n <= 7);
     if (const char *bt = std::getenv("DMAS_BLOCK_TABLES"))
         p->block_tables = M > dmas::kWaveSize || std::atoi(bt) != 0;
-    // the kernel then reads a block's offsets as one scalar block of
-    // table_block_max(n) entries: that caps the block
-    const bool block_tables_mode = dmas::shape_of(p, true).delay == dmas::kDelayTableBlocks;
+    p->block_tables = p->block_tables && p->tables;
     const int C = dmas::kChunk;
     const int H = (L - 1) / 2;
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
     p->row = (p->row + 3) & ~3;
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
-    // envelope: taps, then per-wave rings, or with per-block delay tables
-    // per-wave carries while the rings share the window region
-    const bool share = dmas::rings_share_windows(dmas::shape_of(p, true).delay);
-    const size_t ring_bytes = sizeof(float) * (size_t)W * dmas::ring_stride(H);
-    const size_t env_side = sizeof(float) * (size_t)(dmas::env_taps_len(H) +
-                                                     W * (share ? dmas::carry_stride(H) : dmas::ring_stride(H)));
     const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
-    // Microphones per LDS block: the largest block whose footprint lets three
-    // workgroups share a CU (else two, else one). More blocks cost barriers and
-    // delay evaluations; fewer resident workgroups cost latency hiding.
     // Window elements: (root, sample) pairs when the kernel stages roots
     // (whole-sample delays, n >= 2), else samples.
     const size_t elem = p->roots ? 2 * sizeof(float) : sizeof(float);
-    auto lds_for = [&](int m, bool env = true) {
+    const size_t ring_bytes = sizeof(float) * (size_t)W * dmas::ring_stride(H);
+    // LDS of a workgroup with m microphones per block. Envelope: taps, then
+    // per-wave rings, or (share) per-wave carries while the rings take the
+    // window region after a chunk's last block.
+    auto lds_for = [&](int m, bool env, bool share) {
         const size_t win = elem * (size_t)m * p->row;
-        return fixed + (env ? (share ? std::max(win, ring_bytes) : win) + env_side : win);
+        const size_t side = sizeof(float) * (size_t)(dmas::env_taps_len(H) +
+                                                     W * (share ? dmas::carry_stride(H) : dmas::ring_stride(H)));
+        return fixed + (env ? (share ? std::max(win, ring_bytes) : win) + side : win);
     };
-    const int mb_cap = block_tables_mode ? dmas::table_block_max(n) : dmas::kMaxMicBlock;
+    // With per-block tables the kernel reads a block's offsets as one scalar
+    // block of table_block_max(n) entries: that caps the block.
+    const int mb_cap = p->block_tables ? dmas::table_block_max(n) : dmas::kMaxMicBlock;
+    const int mb_max = std::min(M, mb_cap);
     // Microphones per LDS block, from the envelope kernel's occupancy (its
     // registers, LDS and the wave limit decide): with M <= 64 the largest
     // block that keeps three workgroups per CU (or as many as any block
@@ -688,38 +686,66 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // more microphones the largest block that reaches the highest occupancy
     // (measured: 1024 microphones at order 3 run 7 % faster with 12-microphone
     // blocks at four workgroups per CU than with 16 at three, while 32
-    // microphones run 5 % slower that way).
-    const int mb_max = std::min(M, mb_cap);
+    // microphones run 5 % slower that way). Returns the block (0 if none
+    // fits) and the workgroups per CU at that block.
     const int occ_target = M <= dmas::kWaveSize ? 3 : 1 << 30;
-    int mb = 0, best_occ = 0;
-    for (int cand : {mb_max, 48, 32, 24, 16, 12, 8, 4, 2, 1}) {
-        if (cand > mb_max || lds_for(cand) > lds_cap) continue;
-        dmas::LaunchShape ls = dmas::shape_of(p, true);
-        ls.lds_bytes = lds_for(cand);
-        int occ = 0;
-        e = dmas::launch_plan(n, nullptr, ls, nullptr, &occ);
-        if (e == hipErrorNotSupported) {   // no kernel for these flags: reported at launch
-            occ = (int)(lds_cap / lds_for(cand));
-            e = hipSuccess;
+    auto choose_block = [&](bool share, int *mb_out, int *occ_out) -> hipError_t {
+        p->share_rings = share;
+        int best = 0, best_occ = 0, occ_at_best = 0;
+        for (int cand : {mb_max, 48, 32, 24, 16, 12, 8, 4, 2, 1}) {
+            if (cand > mb_max || lds_for(cand, true, share) > lds_cap) continue;
+            dmas::LaunchShape ls = dmas::shape_of(p, true);
+            ls.lds_bytes = lds_for(cand, true, share);
+            int occ = 0;
+            hipError_t q = dmas::launch_plan(n, nullptr, ls, nullptr, &occ);
+            if (q == hipErrorNotSupported) {   // no kernel for these flags: reported at launch
+                occ = (int)(lds_cap / lds_for(cand, true, share));
+                q = hipSuccess;
+            }
+            if (q != hipSuccess) return q;
+            if (std::min(occ, occ_target) > best_occ) {
+                best_occ = std::min(occ, occ_target);
+                best = cand;
+                occ_at_best = occ;
+            }
         }
-        if (e != hipSuccess) {
-            plan_free(p);
-            return hip_fail(e, "occupancy query");
+        *mb_out = best;
+        *occ_out = occ_at_best;
+        return hipSuccess;
+    };
+    // The rings share the window region only where that buys occupancy or a
+    // larger block (the 1024-microphone frame: 16-microphone blocks at four
+    // workgroups per CU instead of 12; order-3 frames whose windows then fit
+    // four workgroups per CU): elsewhere the carry between chunks and the
+    // extra barrier cost 0.7-2.1 % on the 32-microphone frame.
+    // DMAS_RING_SHARING=0/1 overrides the choice (tuning).
+    int mb = 0, occ_mb = 0;
+    e = choose_block(false, &mb, &occ_mb);
+    if (e == hipSuccess && p->block_tables) {
+        int mb_s = 0, occ_s = 0;
+        e = choose_block(true, &mb_s, &occ_s);
+        bool share = occ_s > occ_mb || (occ_s == occ_mb && mb_s > mb);
+        if (const char *rs = std::getenv("DMAS_RING_SHARING")) share = std::atoi(rs) != 0;
+        if (share) {
+            mb = mb_s;
+            occ_mb = occ_s;
         }
-        if (std::min(occ, occ_target) > best_occ) {
-            best_occ = std::min(occ, occ_target);
-            mb = cand;
-        }
+        p->share_rings = share;
     }
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_fail(e, "occupancy query");
+    }
+    const bool share = p->share_rings;
     if (const char *fixed_mb = std::getenv("DMAS_MIC_BLOCK")) mb = std::max(1, std::min(mb_max, std::atoi(fixed_mb)));
-    if (mb == 0 || lds_for(mb) > lds_cap) {
+    if (mb == 0 || lds_for(mb, true, share) > lds_cap) {
         plan_free(p);
         return fail(DMAS_ERR_UNSUPPORTED,
                     "direction tiles spread over %d samples: the channel window does not fit in LDS", p->halo);
     }
     p->mic_block = mb;
-    p->lds_rf = lds_for(mb, false);
-    p->lds_env = lds_for(mb, true);
+    p->lds_rf = lds_for(mb, false, share);
+    p->lds_env = lds_for(mb, true, share);
     // the kernel derives the same layout from (mic_block, row, H)
     if (p->lds_env != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), true, H, share) ||
         p->lds_rf != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), false, H, share)) {

@@ -76,7 +76,13 @@ struct LaunchShape {
 // of a large table left their latency in the hot loop). The plan picks the
 // block form for more than 64 microphones and for plain FP32 sums up to
 // order 7.
-enum : int { kDelayComputed = 0, kDelayLinear = 1, kDelayTable = 2, kDelayTableBlocks = 3 };
+// kDelayTableBlocksShared is kDelayTableBlocks with the envelope rings in the
+// window region (below), which the plan picks when it raises the occupancy.
+enum : int { kDelayComputed = 0, kDelayLinear = 1, kDelayTable = 2, kDelayTableBlocks = 3, kDelayTableBlocksShared = 4 };
+__host__ __device__ constexpr bool block_tables(int delay)
+{
+    return delay == kDelayTableBlocks || delay == kDelayTableBlocksShared;
+}
 
 // Compile-time tiling shared by host and device: waves (= directions) per
 // workgroup and output samples per lane per chunk.
@@ -117,7 +123,7 @@ __host__ __device__ constexpr int ring_stride(int H) { return (ring_logical(H) +
 __host__ __device__ constexpr int carry_stride(int H) { return (env_prefix(H) + 3) & ~3; }
 // Whether the envelope rings share the window region: a property of the delay
 // mode, so that the other kernels carry none of its address arithmetic.
-__host__ __device__ constexpr bool rings_share_windows(int delay) { return delay == kDelayTableBlocks; }
+__host__ __device__ constexpr bool rings_share_windows(int delay) { return delay == kDelayTableBlocksShared; }
 // Floats of the window region: mic_block rows of `row` elements of elem_floats
 // floats, or the rings if they share it and need more.
 __host__ __device__ constexpr int window_region_floats(int mic_block, int row, int elem_floats, bool env, int H,
@@ -139,7 +145,7 @@ __host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; 
 
 // Batched launch over frames of order n with the given CF / envelope /
 // geometry flags and whole-sample delay mode (kDelayComputed, kDelayTable or
-// kDelayTableBlocks, the same for all frames; plain sums); grid = total
+// kDelayTableBlocks(Shared), the same for all frames; plain sums); grid = total
 // workgroups.
 hipError_t launch_batch(int order, const BatchParams &bp, bool cf, bool env, bool nearfield, int delay,
                         unsigned grid, size_t lds_bytes, hipStream_t stream);

@@ -493,7 +493,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 {
     constexpr bool LINEAR = DM == kDelayLinear;
     constexpr bool TAB = DM == kDelayTable;          // tables through the scalar cache
-    constexpr bool TAB_BLOCKS = DM == kDelayTableBlocks; // offsets and references per block, as scalars
+    constexpr bool TAB_BLOCKS = block_tables(DM); // offsets and references per block, as scalars
     constexpr int W = kDirsPerTile;
     constexpr int K = kSamplesPerLane;
     constexpr int C = kChunk;
@@ -928,7 +928,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //  * none otherwise: Kahan / FP64 sums at orders 6-8 spill 90-280 bytes under
 //    the cap and ran 1.2-6x slower.
 template <int N, int ACC, int DM>
-constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && DM == kDelayTableBlocks)     ? 8
+constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && block_tables(DM))     ? 8
                                  : ACC == kAccF32 ? (N >= 6 || DM == kDelayLinear || DM == kDelayComputed ? 6 : 1)
                                  : (N <= 5 && DM == kDelayTable) ? 6 : 1;
 
@@ -1040,6 +1040,8 @@ hipError_t launch_batch_order(const BatchParams &bp, bool cf, bool env, bool nea
 {
     if (table == kDelayTable) return launch_batch_dm<N, kDelayTable>(bp, cf, env, nearfield, grid, lds, stream);
     if (table == kDelayTableBlocks) return launch_batch_dm<N, kDelayTableBlocks>(bp, cf, env, nearfield, grid, lds, stream);
+    if (table == kDelayTableBlocksShared)
+        return launch_batch_dm<N, kDelayTableBlocksShared>(bp, cf, env, nearfield, grid, lds, stream);
     return launch_batch_dm<N, kDelayComputed>(bp, cf, env, nearfield, grid, lds, stream);
 }
 
@@ -1066,6 +1068,7 @@ hipError_t launch_order(const KernelParams *p, const LaunchShape &s, hipStream_t
     DMAS_CASE(true, true, false, DM, kAccF64)
     DMAS_WHOLE(kDelayTable)
     DMAS_WHOLE(kDelayTableBlocks)
+    DMAS_WHOLE(kDelayTableBlocksShared)
     DMAS_WHOLE(kDelayComputed)
     DMAS_CASE(true, false, false, kDelayLinear, kAccF32)
     DMAS_CASE(true, true, false, kDelayLinear, kAccF32)

@@ -27,6 +27,7 @@ struct dmas_plan_s {
     bool roots = false;    // kernel reads a root plane (whole-sample delays, n >= 2)
     bool tables = false;   // per-tile delay tables (whole-sample delays, <= 2 GiB)
     bool block_tables = false;   // tables read a block of offsets at a time (kDelayTableBlocks)
+    bool share_rings = false;    // with them, the envelope rings in the window region (...Shared)
     int compensated = 0;   // 0 FP32 sums, 1 Kahan FP32, 2 FP64
     int ng_fp64 = 0;
     int dtype = DMAS_F32;
@@ -112,8 +113,9 @@ inline LaunchShape shape_of(const dmas_plan_s *p, bool env)
     ls.nearfield = p->nearfield;
     ls.delay = p->linear ? kDelayLinear
                : !p->tables ? kDelayComputed
-               : p->block_tables ? kDelayTableBlocks
-                                 : kDelayTable;
+               : !p->block_tables ? kDelayTable
+               : p->share_rings   ? kDelayTableBlocksShared
+                                  : kDelayTableBlocks;
     ls.accumulate = p->compensated;
     ls.grid = (unsigned)((int64_t)p->num_tiles * (env ? p->nseg_env : p->nseg_rf));
     ls.lds_bytes = env ? p->lds_env : p->lds_rf;

@@ -221,6 +221,7 @@ hipError_t launch_resident_order(bool cf, bool env, bool nearfield, int delay, c
     DMAS_RES(false, true, true, DM) DMAS_RES(false, false, true, DM)
     DMAS_RES_DM(kDelayTable)
     DMAS_RES_DM(kDelayTableBlocks)
+    DMAS_RES_DM(kDelayTableBlocksShared)
 #undef DMAS_RES_DM
 #undef DMAS_RES
     return hipErrorNotSupported;

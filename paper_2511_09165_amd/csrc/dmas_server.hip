@@ -134,7 +134,7 @@ bool resident_capable(const dmas_plan_s *p, bool env)
 {
     if (!batchable(p) || (p->order != 3 && p->order != 5)) return false;
     const int dm = dmas::shape_of(p, env).delay;
-    return dm == dmas::kDelayTable || dm == dmas::kDelayTableBlocks;
+    return dm == dmas::kDelayTable || dmas::block_tables(dm);
 }
 
 }  // namespace
