@@ -661,7 +661,8 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->row = C + 2 * p->halo + (p->linear ? 1 : 0);
     p->row = (p->row + 3) & ~3;
     const size_t lds_cap = (size_t)prop.sharedMemPerBlock;
-    const size_t fixed = sizeof(int) * dmas::kMaxMicBlock;
+    // reference delays in LDS (kernels that evaluate delays on the device)
+    const size_t fixed = sizeof(int) * dmas::dref_lds_ints(dmas::shape_of(p, true).delay);
     // Window elements: (root, sample) pairs when the kernel stages roots
     // (whole-sample delays, n >= 2), else samples.
     const size_t elem = p->roots ? 2 * sizeof(float) : sizeof(float);
@@ -747,8 +748,9 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     p->lds_rf = lds_for(mb, false, share);
     p->lds_env = lds_for(mb, true, share);
     // the kernel derives the same layout from (mic_block, row, H)
-    if (p->lds_env != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), true, H, share) ||
-        p->lds_rf != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), false, H, share)) {
+    const int delay_mode = dmas::shape_of(p, true).delay;
+    if (p->lds_env != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), true, H, delay_mode) ||
+        p->lds_rf != (size_t)dmas::kernel_lds_bytes(mb, p->row, (int)(elem / sizeof(float)), false, H, delay_mode)) {
         plan_free(p);
         return fail(DMAS_ERR_DEVICE, "internal: LDS layout mismatch");
     }

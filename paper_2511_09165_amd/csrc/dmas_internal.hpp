@@ -99,7 +99,9 @@ __host__ __device__ constexpr int env_lead(int H) { return (H + 31) & ~31; }
 __host__ __device__ constexpr int env_prefix(int H) { return H + env_lead(H); }
 
 // Envelope LDS of a workgroup: after the channel windows come the reference
-// delays (kMaxMicBlock ints), a taps table of env_taps_len(H) floats (kTapLead
+// delays (kMaxMicBlock ints, only in kernels that evaluate delays on the
+// device: the table modes read them as scalars), a taps table of
+// env_taps_len(H) floats (kTapLead
 // zeros, the L = 2H + 1 taps in reverse order, zeros) and one ring per wave of
 // ring_stride(H) floats. With per-block delay tables (more microphones than
 // lanes: many blocks per chunk, where LDS decides the block size) the rings
@@ -133,12 +135,18 @@ __host__ __device__ constexpr int window_region_floats(int mic_block, int row, i
                ? kDirsPerTile * ring_stride(H)
                : mic_block * row * elem_floats;
 }
-// Dynamic LDS bytes of a workgroup.
-__host__ __device__ constexpr int kernel_lds_bytes(int mic_block, int row, int elem_floats, bool env, int H,
-                                                   bool share)
+// Ints of reference delays kept in LDS by a kernel of the given delay mode.
+__host__ __device__ constexpr int dref_lds_ints(int delay)
 {
-    return 4 * (window_region_floats(mic_block, row, elem_floats, env, H, share) + kMaxMicBlock +
-                (env ? env_taps_len(H) + kDirsPerTile * (share ? carry_stride(H) : ring_stride(H)) : 0));
+    return delay == kDelayTable || block_tables(delay) ? 0 : kMaxMicBlock;
+}
+// Dynamic LDS bytes of a workgroup of the given delay mode.
+__host__ __device__ constexpr int kernel_lds_bytes(int mic_block, int row, int elem_floats, bool env, int H, int delay)
+{
+    return 4 * (window_region_floats(mic_block, row, elem_floats, env, H, rings_share_windows(delay)) +
+                dref_lds_ints(delay) +
+                (env ? env_taps_len(H) + kDirsPerTile * (rings_share_windows(delay) ? carry_stride(H) : ring_stride(H))
+                     : 0));
 }
 // Envelope taps on the device: fir_len taps, zero-padded to a multiple of 4.
 __host__ __device__ constexpr int fir_taps_padded(int L) { return (L + 3) & ~3; }

@@ -511,8 +511,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     constexpr bool share = ENV && rings_share_windows(DM);
     const int region = window_region_floats(p.mic_block, p.row, ROOTS ? 2 : 1, ENV, H, share);
     Elem *xwin = reinterpret_cast<Elem *>(smem);                             // mic_block x row
-    int *dref_lds = reinterpret_cast<int *>(smem + region);                  // kMaxMicBlock
-    float *tap_lds = reinterpret_cast<float *>(dref_lds + kMaxMicBlock);     // env_taps_len(H)
+    int *dref_lds = reinterpret_cast<int *>(smem + region);                  // dref_lds_ints(DM)
+    float *tap_lds = reinterpret_cast<float *>(dref_lds + dref_lds_ints(DM)); // env_taps_len(H)
     float *side = tap_lds + env_taps_len(H);
     float *carry = side + wave * carry_stride(H);                            // share: |y| kept between chunks
     float *ring = share ? smem + wave * ring_stride(H)                       // |y| of index i at i + i/16
