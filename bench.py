@@ -466,7 +466,11 @@ def bench_precision(args) -> list:
             for acc, ng64 in (("f32", False), ("f32", True), ("kahan", False), ("kahan", True), ("f64", True)):
                 xin, sc = inputs[dt]
                 with plan_for_frame(base, in_dtype=dt, ng_fp64=ng64, accumulate=acc) as plan:
-                    _, kms = _timed(lambda: plan.envelope(xin, out=out, in_scale=sc), steps, 2, stream)
+                    # plan creation idles the GPU: let the clocks come back before timing
+                    _settle(lambda: plan.envelope(xin, out=out, in_scale=sc), stream, ms=50.0)
+                    # median of three timed runs: a single short run is at the mercy of one stall
+                    kms = float(np.median([_timed(lambda: plan.envelope(xin, out=out, in_scale=sc), steps, 2,
+                                                  stream)[1] for _ in range(3)]))
                 recs.append({"order": n, "storage": dt, "accumulate": acc, "ng_fp64": ng64, "kernel_ms": kms,
                              "value": D * T / (kms * 1e-3)})
     for r in recs:
