@@ -161,6 +161,34 @@ def test_delay_table_matches_per_block_delays(n, nearfield, M, monkeypatch):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("M", [32, 100])
+@pytest.mark.parametrize("n", [2, 3, 5, 7])
+def test_table_layouts_give_the_same_bits(n, M, monkeypatch):
+    """Every way a kernel can read the delay tables and place the envelope rings gives the same
+    envelope bit for bit: offsets one microphone ahead or a block at a time, rings per wave or in
+    the window region, and delays evaluated on the device instead; and it agrees with the oracle (T1)."""
+    f = synth.random_frame(np.random.default_rng(90 + 7 * n + M), M, 45, 1300, n)
+    _say(f"table layouts n={n} M={M}")
+    ref = _run(f, f.x_f32(), env=True)
+    combos = [{"DMAS_RING_SHARING": "0"}, {"DMAS_RING_SHARING": "1"}, {"DMAS_NO_DELAY_TABLE": "1"}]
+    if M <= 64:
+        combos.append({"DMAS_BLOCK_TABLES": "0"})
+    lds = {}
+    for env in combos:
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        with _plan(f) as plan:
+            lds[tuple(env.items())] = plan.info()["lds_bytes"]
+        got = _run(f, f.x_f32(), env=True)
+        for k in env:
+            monkeypatch.delenv(k)
+        assert np.array_equal(got, ref), env
+    # the two ring layouts really are different launches
+    assert lds[(("DMAS_RING_SHARING", "0"),)] != lds[(("DMAS_RING_SHARING", "1"),)]
+    taps = oracle.lowpass_taps(63, 5000.0, f.fs).astype(np.float32).astype(np.float64)
+    check_t1(ref, oracle.envelope(oracle.frame_rows(f, x=f.x_f32().astype(np.float64)), taps))
+
+
 @pytest.mark.parametrize("M,D,T,n", [(1, 1, 1, 1), (3, 1, 2, 3), (5, 9, 63, 2), (8, 8, 255, 5), (8, 8, 256, 5),
                                      (8, 8, 257, 5), (9, 17, 513, 4), (6, 3, 1000, 6)])
 def test_edge_sizes(M, D, T, n):
