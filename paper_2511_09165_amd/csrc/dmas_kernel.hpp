@@ -912,11 +912,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //
 // Register budget: the kernel is compiled for kMinWavesPerSimd waves per SIMD
 // (512 / waves VGPRs; a workgroup puts two waves on each SIMD).
-//  * 8 (64 VGPRs): orders up to 3 with FP32 sums fit it, SGPRs included. With
-//    more than 64 microphones (delay tables read per block) that lets four
-//    workgroups share a CU (measured 8 % faster on the 1024-microphone
-//    near-field frame); with fewer, LDS keeps the kernel at three workgroups
-//    anyway and the tighter budget only costs (2 % on a 32-microphone frame).
+//  * 8 (64 VGPRs): orders up to 3 with FP32 sums and per-block tables fit it,
+//    SGPRs included, which lets four workgroups share a CU where LDS allows
+//    (measured 8 % faster on the 1024-microphone near-field frame, 2.0-2.7 %
+//    at orders 2 and 3 on a 32-microphone frame with the rings in the window
+//    region).
 //  * 6 (80 VGPRs, three workgroups per CU): orders 7 and 8 with FP32 sums
 //    (83 and 95 VGPRs unconstrained) and Kahan / FP64 sums up to order 5 with
 //    scalar-cache tables (87-89). The cap spills 16-56 bytes per lane, which
