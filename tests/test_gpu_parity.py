@@ -245,6 +245,19 @@ def test_ertis_frame_full_size_sampled_rows():
     _say(f"eRTIS-like frame {res} (das peak {np.abs(das).max():.3g})")
 
 
+@pytest.mark.parametrize("n", [2, 3, 7, 8])
+def test_ertis_frame_other_orders_full_size_sampled_rows(n):
+    """The eRTIS-like frame at other orders, full launch, oracle on sampled rows. Each order takes a
+    different kernel layout: orders 2 and 3 the per-block tables with the rings in the window region
+    (four workgroups per CU), order 7 per-block tables with per-wave rings, order 8 tables read one
+    microphone ahead."""
+    f = synth.ertis_frame(order=n)
+    rows = _sample_rows(f, 8, 40 + n)
+    _say(f"eRTIS-like frame order {n} full size, rows {rows[:4]}...")
+    res = _compare(f, f.x_f32(), rows=rows)
+    _say(f"eRTIS-like frame order {n} {res}")
+
+
 def test_nearfield_frame_full_size_sampled_rows():
     """Near field: M=1024 (16 LDS blocks), 64x64x32 voxels, T=2048, order 3 + CF; oracle on sampled rows."""
     f = synth.nearfield_frame()
