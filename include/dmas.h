@@ -257,6 +257,11 @@ dmas_status_t dmas_design_lowpass(int32_t fir_len, double fc, double fs, float *
  *     multi-frame launch (frames with the same CF / envelope / geometry flags,
  *     nearest delays, plain sums; others are launched one by one) on the next
  *     free compute stream, so a new batch starts while earlier ones finish;
+ *     launches go in arrival order, and a new one overlaps a running launch
+ *     only in its last device round, except that a group of at most four
+ *     device rounds of workgroups may start on an idle stream at once
+ *     (DMAS_SMALL_LAUNCH_WGS, read at server creation, sets that limit in
+ *     workgroups; 0 turns it off);
  *   - completion is observed from stream events and stamped per frame.
  * With `resident` set, frames of orders 3 and 5 whose plan reads its delays
  * from tables (nearest delays, plain sums) are served instead by a resident

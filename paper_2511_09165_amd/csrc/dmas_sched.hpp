@@ -6,10 +6,13 @@
 //     any), all of it or none;
 //   * pick_stream: the stream for the next launch, or none while a running
 //     launch is still in its main body;
-//   * pick_group: the admitted frames that share the next launch.
+//   * pick_group: the admitted frames that share the next launch;
+//   * pick_launch: both, and while the gate is closed a small group (a few
+//     device rounds of workgroups at most) on an idle stream.
 // Admission is in arrival order and stops at the first frame that does not
 // fit (no frame overtakes an earlier one); the server applies that rule around
-// grant().
+// grant(). Launches follow arrival order too, with one exception: while the
+// head waits for the gate, a small group may start (pick_launch).
 #pragma once
 
 #include <cstddef>
@@ -137,6 +140,14 @@ inline int pick_stream(const std::vector<StreamState> &streams, double t)
     return s;
 }
 
+// The first idle stream, or -1.
+inline int idle_stream(const std::vector<StreamState> &streams)
+{
+    for (int i = 0; i < (int)streams.size(); ++i)
+        if (!streams[i].busy) return i;
+    return -1;
+}
+
 // What the grouping needs to know of an admitted frame.
 struct Candidate {
     int64_t cls = 0;          // kernel class: frames of one class share an instantiation
@@ -167,6 +178,58 @@ inline std::vector<size_t> pick_group(const std::vector<Candidate> &q, int max_b
         }
     }
     return group;
+}
+
+// The frames of a small launch: the first admitted frame (arrival order) of
+// at most small_cap workgroups, with frames of its class behind it while the
+// launch stays within small_cap workgroups (the rules of pick_group, with
+// small_cap as the cap); empty if no frame is that small.
+inline std::vector<size_t> pick_small(const std::vector<Candidate> &q, int max_batch, int64_t small_cap)
+{
+    for (size_t i = 0; i < q.size(); ++i) {
+        if (q[i].workgroups > small_cap) continue;
+        const std::vector<Candidate> rest(q.begin() + (std::ptrdiff_t)i, q.end());
+        std::vector<size_t> g = pick_group(rest, max_batch, small_cap);
+        for (size_t &k : g) k += i;
+        return g;
+    }
+    return {};
+}
+
+// The next launch: a stream and the frames (indices into the admitted queue,
+// arrival order), or stream -1 when nothing may start at time t.
+//   * The gate is open (pick_stream): the head and the frames grouped with it.
+//   * The gate is closed but a stream is idle: a small group (pick_small, at
+//     most small_cap workgroups). A small launch does not hold the gate, so
+//     the head starts as soon as the gate opens and a stream is free: it waits
+//     at most for one small launch. The small launch shares the compute units
+//     with the running one, which lets a shorter frame finish without waiting
+//     for a long frame's main body.
+struct LaunchPick {
+    int stream = -1;
+    std::vector<size_t> frames;
+    bool small = false;   // started while the gate was closed
+};
+
+inline LaunchPick pick_launch(const std::vector<StreamState> &streams, double t, const std::vector<Candidate> &q,
+                              int max_batch, int64_t wg_cap, int64_t small_cap)
+{
+    LaunchPick r;
+    if (q.empty()) return r;
+    const int s = pick_stream(streams, t);
+    if (s >= 0) {
+        r.stream = s;
+        r.frames = pick_group(q, max_batch, wg_cap);
+        return r;
+    }
+    const int idle = idle_stream(streams);
+    if (idle < 0 || small_cap <= 0) return r;
+    r.frames = pick_small(q, max_batch, small_cap);
+    if (!r.frames.empty()) {
+        r.stream = idle;
+        r.small = true;
+    }
+    return r;
 }
 
 }  // namespace sched

@@ -67,7 +67,8 @@ struct Scenario {
     size_t budget = 64u << 20;
     int nstreams = 2;
     int max_batch = 16;
-    int64_t wg_cap = 1536;
+    int64_t wg_cap = 1536;      // about two device rounds
+    int64_t small_cap = 3072;   // four device rounds: such a group may start while the gate is closed
     int n_plans = 8;
     bool oversize = false;      // some frames larger than the budget
 };
@@ -136,7 +137,7 @@ int main(int argc, char **argv)
     std::deque<int> queued, admitted;
     std::vector<Launch> launches(sc.nstreams);
     int next_arrival = 0, launch_seq = 0, done_seq = 0, admit_seq = 0;
-    int64_t rejected = 0, waits_for_memory = 0, n_launches = 0, batched = 0, max_group = 0;
+    int64_t rejected = 0, waits_for_memory = 0, n_launches = 0, batched = 0, max_group = 0, n_small = 0;
     size_t max_used = 0;
     std::vector<int> admit_order;
 
@@ -263,27 +264,41 @@ int main(int argc, char **argv)
         while (!admitted.empty()) {
             std::vector<sched::StreamState> ss;
             for (auto &l : launches) ss.push_back({l.busy, l.tail_start});
-            const int s = sched::pick_stream(ss, now);
-            if (s < 0) break;
-            CHECK(!launches[s].busy, "picked a busy stream");
-            for (auto &l : launches) CHECK(!l.busy || l.tail_start <= now, "launch overlaps a running main body");
             std::vector<sched::Candidate> cand;
             for (int id : admitted) {
                 const Plan &pl = plans[frames[id].plan];
                 cand.push_back({pl.cls, pl.batchable, pl.workgroups});
             }
-            const std::vector<size_t> pick = sched::pick_group(cand, sc.max_batch, sc.wg_cap);
-            CHECK(!pick.empty() && pick[0] == 0, "the head of the queue must lead its launch");
+            const sched::LaunchPick lp = sched::pick_launch(ss, now, cand, sc.max_batch, sc.wg_cap, sc.small_cap);
+            if (lp.stream < 0) break;
+            const int s = lp.stream;
+            const std::vector<size_t> &pick = lp.frames;
+            CHECK(!launches[s].busy, "picked a busy stream");
+            CHECK(!pick.empty(), "a launch without frames");
+            bool gate_closed = false;
+            for (auto &l : launches) gate_closed = gate_closed || (l.busy && l.tail_start > now);
+            if (!lp.small) {
+                CHECK(!gate_closed, "launch overlaps a running main body");
+                CHECK(pick[0] == 0, "the head of the queue must lead its launch");
+            } else {
+                // only while the gate is closed, led by the first frame that small
+                CHECK(gate_closed, "a small launch while the gate is open");
+                for (size_t k = 0; k < pick[0]; ++k)
+                    CHECK(cand[k].workgroups > sc.small_cap, "a small launch skipped an earlier small frame");
+                ++n_small;
+            }
             int64_t wgs = 0;
             for (size_t k = 0; k < pick.size(); ++k) {
                 CHECK(k == 0 || pick[k] > pick[k - 1], "group out of arrival order");
                 const sched::Candidate &c = cand[pick[k]];
-                CHECK(c.cls == cand[0].cls, "frames of two kernel classes in one launch");
+                CHECK(c.cls == cand[pick[0]].cls, "frames of two kernel classes in one launch");
                 wgs += c.workgroups;
             }
+            if (lp.small) CHECK(wgs <= sc.small_cap, "small launch of %lld workgroups", (long long)wgs);
             if (pick.size() > 1) {
                 CHECK((int)pick.size() <= sc.max_batch, "more than max_batch frames");
-                CHECK(wgs <= sc.wg_cap, "batch of %lld workgroups over the cap", (long long)wgs);
+                // a small launch packs up to its own cap (checked above)
+                CHECK(lp.small || wgs <= sc.wg_cap, "batch of %lld workgroups over the cap", (long long)wgs);
                 for (size_t k : pick) CHECK(cand[k].batchable, "a frame the multi-frame kernel does not serve");
             }
             double work = 0;
@@ -305,7 +320,7 @@ int main(int argc, char **argv)
             const double dur = work * (0.7 + 0.6 * U(rng));   // durations vary: completions reorder
             l.busy = true;
             l.end = now + dur;
-            l.tail_start = now + 0.8 * dur;
+            l.tail_start = lp.small ? now : now + 0.8 * dur;   // a small launch does not hold the gate
         }
     }
 
@@ -326,8 +341,10 @@ int main(int argc, char **argv)
             }
     std::printf("{\"scenario\": \"%s\", \"frames\": %d, \"done\": %d, \"rejected\": %lld, \"launches\": %lld, "
                 "\"batched_frames\": %lld, \"max_group\": %lld, \"waits_for_memory\": %lld, "
-                "\"completed_out_of_launch_order\": %lld, \"max_used\": %zu, \"budget\": %zu}\n",
+                "\"completed_out_of_launch_order\": %lld, \"max_used\": %zu, \"budget\": %zu, "
+                "\"small_launches\": %lld}\n",
                 name.c_str(), total, done, (long long)rejected, (long long)n_launches, (long long)batched,
-                (long long)max_group, (long long)waits_for_memory, (long long)reordered, max_used, sc.budget);
+                (long long)max_group, (long long)waits_for_memory, (long long)reordered, max_used, sc.budget,
+                (long long)n_small);
     return 0;
 }

@@ -8,8 +8,10 @@ UndefinedBehaviorSanitizer. It checks, after every step, that granted device
 ranges never overlap or leave the budget, that admission follows arrival
 order (a frame that does not fit blocks the ones behind it), that every
 launch holds one kernel class within the frame and workgroup caps and is led
-by the head of the queue, and at the end that every admissible frame
-finished and the arena coalesced back to one free range.
+by the head of the queue, except small launches (at most four device rounds
+of workgroups) that start only while the gate is closed and are led by the
+first frame that small, and at the end that every admissible frame finished
+and the arena coalesced back to one free range.
 """
 
 import json
@@ -53,6 +55,7 @@ def test_mixed_stream(sim, seed):
     assert out["max_used"] <= out["budget"]
     assert out["batched_frames"] > 0 and out["max_group"] > 1            # small frames were packed
     assert out["completed_out_of_launch_order"] >= 1                     # streams finish in any order
+    assert out["small_launches"] > 0                                     # small frames went beside long ones
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -78,6 +81,7 @@ def test_one_plain_launch_per_frame(sim):
     assert r.returncode == 0, r.stderr
     out = json.loads(r.stdout)
     assert out["launches"] == out["frames"] and out["max_group"] == 1 and out["batched_frames"] == 0
+    assert out["small_launches"] == 0                                    # one stream: nothing runs beside
 
 
 def test_checks_catch_a_planted_overtake(tmp_path):

@@ -64,8 +64,10 @@ def _blocker():
     return f
 
 
-def test_batched_equals_alone_bitwise():
+def test_batched_equals_alone_bitwise(monkeypatch):
     from paper_2511_09165_amd import plan_for_frame
+    # no small launches beside the blocker: the frames behind it wait for the gate and are packed
+    monkeypatch.setenv("DMAS_SMALL_LAUNCH_WGS", "0")
     frames = [_blocker()] + _mix(1, 12)
     plans = [plan_for_frame(f, env_decimation=(4 if k % 5 == 2 else 1)) for k, f in enumerate(frames)]
     alone = [_standalone(p, f.x_f32(), f.env) for f, p in zip(frames, plans)]
@@ -89,10 +91,11 @@ def test_batched_equals_alone_bitwise():
         p.close()
 
 
-def test_large_arrays_batched_bitwise():
+def test_large_arrays_batched_bitwise(monkeypatch):
     """Frames of more than 64 microphones (delay offsets read per microphone block) in multi-frame
     launches: the same bits as alone, next to frames of 64 or fewer microphones."""
     from paper_2511_09165_amd import plan_for_frame
+    monkeypatch.setenv("DMAS_SMALL_LAUNCH_WGS", "0")   # pack the frames that queue behind the blocker
     rng = np.random.default_rng(7)
     frames = [_blocker()]
     # runs of the same kernel class (order, geometry), which the server packs together
@@ -111,6 +114,36 @@ def test_large_arrays_batched_bitwise():
         assert np.array_equal(a, b), f"frame {k} differs between alone and batched"
     assert stats["completed"] == len(frames) and stats["failed"] == 0
     assert max(i["batch_frames"] for i in infos[1:]) > 1, "no batching happened"
+    for p in plans:
+        p.close()
+
+
+def test_small_frames_start_beside_a_long_one():
+    """While a long frame runs its main body, small frames (here at most one device round of
+    workgroups) start on the idle stream instead of waiting for it, and give the same bits as alone."""
+    from paper_2511_09165_amd import plan_for_frame
+    long_frame = synth.random_frame(np.random.default_rng(98), 64, 8192, 16384, 5)
+    long_frame.env = True
+    rng = np.random.default_rng(11)
+    small = []
+    for _ in range(6):
+        f = synth.random_frame(rng, 16, int(rng.integers(16, 64)), 2048, 3)
+        f.env = True
+        small.append(f)
+    frames = [long_frame] + small
+    plans = [plan_for_frame(f) for f in frames]
+    for p in plans[1:]:
+        assert p.info()["workgroups"] <= 3 * 256, "not a small frame"
+    alone = [_standalone(p, f.x_f32(), f.env) for f, p in zip(frames, plans)]
+    _say("serving: small frames beside a long one")
+    outs, infos, stats = _run_server(frames, plans, hbm_budget=8 << 30, num_streams=2, max_batch=64)
+    for k, (a, b) in enumerate(zip(alone, outs)):
+        assert np.array_equal(a, b), f"frame {k} differs between alone and beside the long frame"
+    assert stats["completed"] == len(frames) and stats["failed"] == 0
+    t0, t1 = infos[0]["t_launch"], infos[0]["t_done"]
+    early = [i for i in infos[1:] if i["t_done"] < t0 + 0.5 * (t1 - t0)]
+    assert early, ("no small frame finished in the first half of the long one", t0, t1,
+                   [(i["t_launch"], i["t_done"]) for i in infos[1:]])
     for p in plans:
         p.close()
 
