@@ -224,17 +224,17 @@ def _base_record(args, value, ms_per_step, dtype, config) -> dict:
             "dtype": dtype, "data": "synthetic (seeded)", "config": config}
 
 
-def _settle(launch, stream, ms: float = 250.0) -> int:
+def _settle(launch, stream, ms: float = 250.0, batch: int = 16) -> int:
     """Untimed launches until ``ms`` of device time have passed, so the GPU clocks have ramped up
     before the warmup steps (a handful of steps after plan creation still runs at lower clocks).
     Returns the number of launches (reported in the JSON line as clock_settle)."""
     import torch
     done, t0 = 0, time.perf_counter()
     while (time.perf_counter() - t0) * 1e3 < ms:
-        for _ in range(16):
+        for _ in range(batch):
             launch()
         torch.cuda.synchronize()
-        done += 16
+        done += batch
     return done
 
 
@@ -250,7 +250,7 @@ def _computed_delay_ms(frame, fir_len: int, reps: int, stream, x, out) -> dict:
         try:
             with plan_for_frame(frame, fir_len=fir_len) as p:
                 info = p.info()
-                _timed(lambda: p.envelope(x, out=out), reps, 2, stream)   # clocks and caches
+                _settle(lambda: p.envelope(x, out=out), stream, 50.0, batch=min(16, reps))   # clocks, caches
                 res[f"{key}_ms"] = _timed(lambda: p.envelope(x, out=out), reps, 2, stream)[1]
                 res[f"{key}_delay_table_bytes"] = info["delay_table_bytes"]
         finally:
@@ -288,11 +288,15 @@ def bench_headline(args) -> dict:
                            "note": "untimed launches before the warmup steps while the GPU clocks ramp up"}
     rec["roofline"] = _roofline(launch_slots(M, T, D, n, True), pixels, kernel_ms,
                                 measured_traffic(workload_key), fir=fir_flops(D, T, fir_len))
-    # per-launch statistics of the same call, then the RF image and CF off (the paper's Table III ratio)
-    reps = max(5, args.steps // 2)
+    # per-launch statistics of the same call, then the RF image and CF off (the paper's Table III
+    # ratio); each of these legs settles the clocks again (plan creation and host waits let them
+    # drop) and times at least 100 launches, whatever --steps is
+    reps = max(100, args.steps // 2)
     rec["launch_stats"] = _launch_stats(lambda: plan.envelope(x, out=out), reps, stream)
+    _settle(lambda: plan.beamform(x, out=out), stream, 50.0)
     extra = {"rf_ms": _timed(lambda: plan.beamform(x, out=out), reps, 2, stream)[1]}
     with plan_for_frame(frame, fir_len=fir_len, use_cf=False) as p2:
+        _settle(lambda: p2.envelope(x, out=out), stream, 50.0)
         extra["no_cf_env_ms"] = _timed(lambda: p2.envelope(x, out=out), reps, 2, stream)[1]
     extra["cf_cost"] = kernel_ms / extra["no_cf_env_ms"] - 1.0
     if not args.no_delay_modes:
