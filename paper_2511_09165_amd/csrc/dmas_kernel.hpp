@@ -916,7 +916,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //    SGPRs included, which lets four workgroups share a CU where LDS allows
 //    (measured 8 % faster on the 1024-microphone near-field frame, 2.0-2.7 %
 //    at orders 2 and 3 on a 32-microphone frame with the rings in the window
-//    region).
+//    region); so do the near-field kernels with delays computed on the device
+//    (74 VGPRs unconstrained, 63 with no spill under the cap: 1.9 % faster on
+//    the near-field frame; the far-field ones stay at 6, where the
+//    32-microphone frame's LDS allows only three workgroups per CU anyway and
+//    the cap cost 1.3-2.6 %).
 //  * 6 (80 VGPRs, three workgroups per CU): orders 7 and 8 with FP32 sums
 //    (83 and 95 VGPRs unconstrained) and Kahan / FP64 sums up to order 5 with
 //    scalar-cache tables (87-89). The cap spills 16-56 bytes per lane, which
@@ -927,13 +931,14 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //    and fit the cap with no spill (8 bytes for near-field linear delays).
 //  * none otherwise: Kahan / FP64 sums at orders 6-8 spill 90-280 bytes under
 //    the cap and ran 1.2-6x slower.
-template <int N, int ACC, int DM>
-constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && block_tables(DM))     ? 8
+template <int N, int ACC, int DM, bool NEAR>
+constexpr int kMinWavesPerSimd = (N <= 3 && ACC == kAccF32 && (block_tables(DM) || (NEAR && DM == kDelayComputed)))
+                                     ? 8
                                  : ACC == kAccF32 ? (N >= 6 || DM == kDelayLinear || DM == kDelayComputed ? 6 : 1)
                                  : (N <= 5 && DM == kDelayTable) ? 6 : 1;
 
 template <int N, bool CF, bool ENV, bool NEAR, int DM, int ACC>
-__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, ACC, DM>))
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, ACC, DM, NEAR>))
 dmas_kernel(const KernelParams p)
 {
     extern __shared__ float smem[];
@@ -944,7 +949,7 @@ dmas_kernel(const KernelParams p)
 // parameters (all of order N) and the first workgroup index of each frame
 // (ascending); each workgroup finds its frame by binary search.
 template <int N, bool CF, bool ENV, bool NEAR, int DM>
-__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, kAccF32, DM>))
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, kAccF32, DM, NEAR>))
 dmas_batch_kernel(const BatchParams bp)
 {
     extern __shared__ float smem[];

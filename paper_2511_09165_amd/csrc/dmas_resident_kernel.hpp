@@ -92,7 +92,7 @@ __device__ __forceinline__ void roots_item(const ResidentJob &jd, int item)
 }
 
 template <int N, bool CF, bool ENV, bool NEAR, int DM>
-__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, kAccF32, DM>))
+__global__ void __launch_bounds__(kDirsPerTile * kWaveSize, (kMinWavesPerSimd<N, kAccF32, DM, NEAR>))
 dmas_resident_kernel(const ResidentArgs a)
 {
     extern __shared__ float smem[];
