@@ -551,13 +551,21 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     //  * M <= 64 without tables (linear delays): lane i of every wave computes
     //    its direction's delay for microphone i once, and wave 0 (the tile's
     //    reference direction) publishes its delays in LDS for the staging step;
-    //  * otherwise the same per block of microphones (lane i holding
-    //    microphone i of the block), once per block and chunk.
+    //  * otherwise the same per group of blocks (lane i holding microphone i
+    //    of the group; the largest power of two of blocks that fits the
+    //    lanes), once per group and chunk; each block takes its microphones'
+    //    delays from their lanes.
     // Without tables, after a barrier each lane turns (delay - reference
     // delay) into its LDS offset.
     typedef const __attribute__((address_space(4))) int32_t const_i32;
     constexpr bool table = TAB;   // p.tile_off and p.tile_dref are set (also with TAB_BLOCKS)
     const bool all_mics = !table && !TAB_BLOCKS && p.M <= kWaveSize;
+    // groups of device-computed delays: 2^group_shift blocks (one group of
+    // every block when each microphone has a lane)
+    const int group_shift = all_mics ? 0 : 31 - __builtin_clz(max(1, kWaveSize / p.mic_block));
+    // block blk's index within its group, and the lane of its microphone 0
+    auto group_pos = [&](int blk) { return all_mics ? blk : blk & ((1 << group_shift) - 1); };
+    auto group_lane = [&](int blk) { return group_pos(blk) * p.mic_block; };
     const_i32 *off_row = table ? reinterpret_cast<const_i32 *>(
                                      reinterpret_cast<uintptr_t>(p.tile_off + ((size_t)tile * W + wave) * p.M))
                                : nullptr;
@@ -591,7 +599,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             sdref1 = (wave + W < p.mic_block && r0 + W < p.M) ? dref_row[r0 + W] : 0;
             return;
         }
-        const int nlanes = all_mics ? p.M : p.mic_block;
+        // the first block of a group computes the group's delays
+        if (group_pos(blk) != 0) return;
+        const int nlanes = all_mics ? p.M : p.mic_block << group_shift;
         if (lane < nlanes) {
             if (mic < p.M) {
                 mydw = steer_whole<NEAR, LINEAR>(p.mic + 3 * mic, vdir, p.fs, p.c, &myfrac);
@@ -604,16 +614,17 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     // Reference delay of microphone i (wave-uniform) of block blk, for staging.
     auto dref_of = [&](int blk, int i) {
         if constexpr (TAB_BLOCKS) return i == wave ? sdref0 : sdref1;
-        return table ? dref_row[blk * p.mic_block + i] : dref_lds[all_mics ? blk * p.mic_block + i : i];
+        return table ? dref_row[blk * p.mic_block + i] : dref_lds[group_lane(blk) + i];
     };
     auto block_offsets = [&](int blk) {
         if (table || TAB_BLOCKS) return;
         const int mic = blk * p.mic_block + lane;
+        // this lane's microphone sits in lane `src_lane` of the group's delays
+        const int src_lane = group_lane(blk) + lane;
         int dw = mydw;
         float fr = myfrac;
-        if (all_mics) {
-            // this lane's microphone sits in lane `mic` of the cached delays
-            const int src = min(mic, p.M - 1) << 2;
+        if (all_mics || group_shift > 0) {
+            const int src = min(src_lane, all_mics ? p.M - 1 : kWaveSize - 1) << 2;
             dw = __builtin_amdgcn_ds_bpermute(src, mydw);
             if constexpr (LINEAR)
                 fr = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, myfrac)));
@@ -621,7 +632,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         if (lane < p.mic_block) {
             int rel = 0;
             if (mic < p.M)
-                rel = min(max(dw - dref_lds[all_mics ? mic : lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
+                rel = min(max(dw - dref_lds[src_lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
             myoff = lane * p.row + rel;
             if constexpr (LINEAR) myfrac_blk = fr;
         }
