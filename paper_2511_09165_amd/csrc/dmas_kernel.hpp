@@ -553,10 +553,11 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     //    reference direction) publishes its delays in LDS for the staging step;
     //  * otherwise the same per group of blocks (lane i holding microphone i
     //    of the group; the largest power of two of blocks that fits the
-    //    lanes), once per group and chunk; each block takes its microphones'
-    //    delays from their lanes.
-    // Without tables, after a barrier each lane turns (delay - reference
-    // delay) into its LDS offset.
+    //    lanes), once per group and chunk.
+    // Without tables, after the barrier that publishes the reference delays
+    // each lane turns (delay - reference delay) into its window's LDS offset,
+    // and the hot loop reads microphone i's from lane (first lane of the
+    // block) + i.
     typedef const __attribute__((address_space(4))) int32_t const_i32;
     constexpr bool table = TAB;   // p.tile_off and p.tile_dref are set (also with TAB_BLOCKS)
     const bool all_mics = !table && !TAB_BLOCKS && p.M <= kWaveSize;
@@ -583,9 +584,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     // this wave stages, wave and wave + W of the block
     int sdref0 = 0, sdref1 = 0;
     int mydw = 0;
-    int myoff = 0;
     float myfrac = 0.0f;      // fraction of mydw's microphone (linear delays)
-    float myfrac_blk = 0.0f;  // fraction of microphone `lane` of the current block
+    int myoff = 0;            // LDS element where mydw's microphone's window starts
     auto block_geometry = [&](int blk) {
         if (table) return;
         const int mic = blk * p.mic_block + lane;
@@ -616,25 +616,17 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         if constexpr (TAB_BLOCKS) return i == wave ? sdref0 : sdref1;
         return table ? dref_row[blk * p.mic_block + i] : dref_lds[group_lane(blk) + i];
     };
+    // At a group's first block (after the barrier that publishes the reference
+    // delays): each lane's microphone (row lane % mic_block of its block's
+    // windows) gets the LDS element where its window starts.
     auto block_offsets = [&](int blk) {
         if (table || TAB_BLOCKS) return;
+        if (group_pos(blk) != 0) return;
         const int mic = blk * p.mic_block + lane;
-        // this lane's microphone sits in lane `src_lane` of the group's delays
-        const int src_lane = group_lane(blk) + lane;
-        int dw = mydw;
-        float fr = myfrac;
-        if (all_mics || group_shift > 0) {
-            const int src = min(src_lane, all_mics ? p.M - 1 : kWaveSize - 1) << 2;
-            dw = __builtin_amdgcn_ds_bpermute(src, mydw);
-            if constexpr (LINEAR)
-                fr = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src, __builtin_bit_cast(int, myfrac)));
-        }
-        if (lane < p.mic_block) {
-            int rel = 0;
-            if (mic < p.M)
-                rel = min(max(dw - dref_lds[src_lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
-            myoff = lane * p.row + rel;
-            if constexpr (LINEAR) myfrac_blk = fr;
+        const int nlanes = all_mics ? p.M : p.mic_block << group_shift;
+        if (lane < nlanes && mic < p.M) {
+            const int row = lane - (lane / p.mic_block) * p.mic_block;
+            myoff = row * p.row + min(max(mydw - dref_lds[lane] + p.halo, 0), two_halo);  // the measured halo keeps this in range
         }
     };
 
@@ -820,7 +812,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                         }
                     } else if constexpr (LINEAR) {
                         const float fr = __builtin_bit_cast(
-                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myfrac_blk), i));
+                            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, myfrac), group_lane(blk) + i));
                         float v0[K], v1[K];
 #pragma unroll
                         for (int j = 0; j < K; ++j) {
@@ -867,11 +859,13 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                     for (int i = 1; i < LB; ++i)
                         if (i < nm) mic_step(rest_t{}, i, soff[i]);
                 } else {
+                    const int g0 = group_lane(blk);
+                    auto off_of = [&](int i) { return __builtin_amdgcn_readlane(myoff, g0 + i); };
                     if (PEEL && blk == 0) {
-                        mic_step(first_t{}, 0, __builtin_amdgcn_readlane(myoff, 0));
-                        for (int i = 1; i < nm; ++i) mic_step(rest_t{}, i, __builtin_amdgcn_readlane(myoff, i));
+                        mic_step(first_t{}, 0, off_of(0));
+                        for (int i = 1; i < nm; ++i) mic_step(rest_t{}, i, off_of(i));
                     } else {
-                        for (int i = 0; i < nm; ++i) mic_step(rest_t{}, i, __builtin_amdgcn_readlane(myoff, i));
+                        for (int i = 0; i < nm; ++i) mic_step(rest_t{}, i, off_of(i));
                     }
                 }
             }
