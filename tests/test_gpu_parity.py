@@ -161,6 +161,26 @@ def test_delay_table_matches_per_block_delays(n, nearfield, M, monkeypatch):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("mb", [4, 8, 12, 24, 33])
+@pytest.mark.parametrize("nearfield", [False, True])
+def test_device_delays_any_block_size(mb, nearfield, monkeypatch):
+    """Delays evaluated on the device for more microphones than lanes are computed for a group of
+    blocks at a time (sixteen to one blocks of mb microphones, the last group partial at M = 150): the
+    envelope equals, bit for bit, that of the plan-time tables, and with linear delays that of the
+    default block size."""
+    f = synth.random_frame(np.random.default_rng(300 + mb + 7 * nearfield), 150, 29, 700, 3, nearfield=nearfield)
+    _say(f"device delays mb={mb} near={nearfield}")
+    ref = _run(f, f.x_f32(), env=True)
+    lin_ref = _run(f, f.x_f32(), env=True, linear=True)
+    monkeypatch.setenv("DMAS_MIC_BLOCK", str(mb))
+    monkeypatch.setenv("DMAS_NO_DELAY_TABLE", "1")
+    with _plan(f) as plan:
+        info = plan.info()
+        assert info["mics_per_block"] == mb and info["delay_table_bytes"] == 0
+    np.testing.assert_array_equal(_run(f, f.x_f32(), env=True), ref)
+    np.testing.assert_array_equal(_run(f, f.x_f32(), env=True, linear=True), lin_ref)
+
+
 @pytest.mark.parametrize("M", [32, 100])
 @pytest.mark.parametrize("n", [2, 3, 5, 7])
 def test_table_layouts_give_the_same_bits(n, M, monkeypatch):
