@@ -53,10 +53,27 @@ namespace dmas {
 // of IEEE double operations with contraction disabled, so that the whole-sample
 // rounding is reproducible on any IEEE machine that evaluates the same steps.
 // ---------------------------------------------------------------------------
+// |v| of a near-field focal point (its distance from the origin, where the
+// delays are referenced), by the same steps as the delay uses; 0 in the far
+// field. A kernel evaluates it once per direction instead of once per delay.
 template <bool NEAR>
-__device__ __forceinline__ double steer_samples(const double *__restrict__ r,
-                                                const double *__restrict__ v,
-                                                double fs, double c)
+__device__ __forceinline__ double steer_origin(const double *__restrict__ v)
+{
+#pragma clang fp contract(off)
+    if constexpr (!NEAR) {
+        return 0.0;
+    } else {
+        double q0 = v[0] * v[0];
+        q0 = q0 + v[1] * v[1];
+        q0 = q0 + v[2] * v[2];
+        return __builtin_sqrt(q0);
+    }
+}
+
+// vnorm = steer_origin<NEAR>(v).
+template <bool NEAR>
+__device__ __forceinline__ double steer_samples(const double *__restrict__ r, const double *__restrict__ v,
+                                                double vnorm, double fs, double c)
 {
 #pragma clang fp contract(off)
     double tau;
@@ -74,21 +91,19 @@ __device__ __forceinline__ double steer_samples(const double *__restrict__ r,
         double q = dx * dx;
         q = q + dy * dy;
         q = q + dz * dz;
-        double q0 = v[0] * v[0];
-        q0 = q0 + v[1] * v[1];
-        q0 = q0 + v[2] * v[2];
-        tau = (__builtin_sqrt(q) - __builtin_sqrt(q0)) / c;
+        tau = (__builtin_sqrt(q) - vnorm) / c;
     }
     return fs * tau;
 }
 
 // Whole-sample part used to address the channel: nearest sample
 // (floor(f + 1/2)) or, for linear interpolation, floor(f) plus the fraction.
+// vnorm = steer_origin<NEAR>(v).
 template <bool NEAR, bool LINEAR>
-__device__ __forceinline__ int steer_whole(const double *r, const double *v, double fs,
-                                           double c, float *frac)
+__device__ __forceinline__ int steer_whole(const double *r, const double *v, double vnorm, double fs, double c,
+                                           float *frac)
 {
-    const double f = steer_samples<NEAR>(r, v, fs, c);
+    const double f = steer_samples<NEAR>(r, v, vnorm, fs, c);
     if constexpr (LINEAR) {
         const double q = __builtin_floor(f);
         *frac = (float)(f - q);
@@ -97,6 +112,12 @@ __device__ __forceinline__ int steer_whole(const double *r, const double *v, dou
         *frac = 0.0f;
         return (int)__builtin_floor(f + 0.5);
     }
+}
+
+template <bool NEAR, bool LINEAR>
+__device__ __forceinline__ int steer_whole(const double *r, const double *v, double fs, double c, float *frac)
+{
+    return steer_whole<NEAR, LINEAR>(r, v, steer_origin<NEAR>(v), fs, c, frac);
 }
 
 // ---------------------------------------------------------------------------
@@ -522,6 +543,15 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
     const int dir0 = __builtin_amdgcn_readfirstlane(p.tile_dirs[tile * W]);
     const bool active = dir >= 0;
     const double *vdir = p.dirs + 3 * (active ? dir : dir0);
+    // |v| of this wave's direction (near field), for the delays evaluated on
+    // the device; wave-uniform, kept in scalar registers
+    const double vnorm = [&] {
+        const double v = steer_origin<NEAR>(vdir);
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+        return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    }();
 
     // The workgroup's outputs are [g0, g1) (g0 a multiple of 32). Pass ch
     // covers the samples [tc, tc + C), tc = ystart + ch * C, and outputs
@@ -604,7 +634,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
         const int nlanes = all_mics ? p.M : p.mic_block << group_shift;
         if (lane < nlanes) {
             if (mic < p.M) {
-                mydw = steer_whole<NEAR, LINEAR>(p.mic + 3 * mic, vdir, p.fs, p.c, &myfrac);
+                mydw = steer_whole<NEAR, LINEAR>(p.mic + 3 * mic, vdir, vnorm, p.fs, p.c, &myfrac);
                 if (wave == 0) dref_lds[lane] = mydw;
             } else if (wave == 0) {
                 dref_lds[lane] = 0;
