@@ -225,31 +225,27 @@ __global__ void __launch_bounds__(256) root_plane_kernel(const void *__restrict_
 }
 
 // One microphone's window [base, base + row) of the root plane starting at
-// element chan, (0, 0) outside [0, T) (the pair of a zero sample).
+// element chan, (0, 0) outside [0, T) (the pair of a zero sample). A window
+// inside the record (all but the first and last chunks) is copied by the
+// global-to-LDS loads: each lane moves 16 bytes (two pairs) straight into LDS
+// at M0 + 16 * lane, a wave 1 KiB per load, with no vector registers and no
+// vector ALU work; row is a multiple of 4 pairs, so the copy is whole 16-byte
+// pieces into 32-byte aligned LDS rows. Those copies complete in the
+// background (the wave's vmcnt): the caller waits for them before the barrier
+// that publishes the windows. (Against loading into registers and writing
+// them to LDS: 4.0-7.5 % faster across the kernels, bitwise the same.)
 __device__ __forceinline__ void stage_row_roots(float2 *__restrict__ dst, const float2 *__restrict__ plane,
                                                 size_t chan, int base, int row, int T, int lane)
 {
     if (base >= 0 && base + row <= T) {
-        // The window's start is wave-uniform and each lane adds a 32-bit byte
-        // offset, so the loads take a scalar base address and the per-row
-        // address arithmetic stays on the scalar unit.
+        typedef __attribute__((address_space(3))) void lds_void;
         const char *src = reinterpret_cast<const char *>(plane + chan + (size_t)base);
-        auto at = [&](int r) {
-            const unsigned off = (unsigned)lane * 8u + (unsigned)r * (8u * kWaveSize);
-            return *reinterpret_cast<const float2 *>(src + off);
-        };
-        float2 *d = dst + lane;
-        const int full = row / kWaveSize;   // whole wave-wide steps (wave-uniform)
-        int r = 0;
-        for (; r + 4 <= full; r += 4) {
-            const float2 a0 = at(r + 0), a1 = at(r + 1), a2 = at(r + 2), a3 = at(r + 3);
-            d[(r + 0) * kWaveSize] = a0;
-            d[(r + 1) * kWaveSize] = a1;
-            d[(r + 2) * kWaveSize] = a2;
-            d[(r + 3) * kWaveSize] = a3;
+        const int pieces = row >> 1;
+        for (int q = 0; q < pieces; q += kWaveSize) {   // wave-uniform
+            if (lane < pieces - q)
+                __builtin_amdgcn_global_load_lds(src + (unsigned)(q + lane) * 16u, (lds_void *)(dst + 2 * q), 16, 0,
+                                                 0);
         }
-        for (; r < full; ++r) d[r * kWaveSize] = at(r);
-        if (lane < row - full * kWaveSize) d[full * kWaveSize] = at(full);
     } else {
         for (int r = lane; r < row; r += kWaveSize) {
             const int t = base + r;
@@ -822,6 +818,8 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                 }
             }
             if (prio_staging) __builtin_amdgcn_s_setprio(0);
+            // this wave's global-to-LDS copies have landed (vmcnt(0), the other counters untouched)
+            if constexpr (ROOTS) __builtin_amdgcn_s_waitcnt(0x0F70);
             __syncthreads();
             // ---- hot loop: delayed samples -> roots -> power sums ----
             if (active) {
