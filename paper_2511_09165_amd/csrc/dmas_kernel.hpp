@@ -807,11 +807,9 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
             __syncthreads();  // reference delays visible; previous block's reads done
             block_offsets(blk);
             // ---- stage this block's channel windows into LDS ----
-            // With many small blocks (more than 64 microphones) the waves issue
-            // their window loads at raised priority, so the loads go out early
-            // (0.9 % on the 1024-microphone frame; 0.4 % slower with 32).
-            const bool prio_staging = TAB_BLOCKS && p.M > kWaveSize;
-            if (prio_staging) __builtin_amdgcn_s_setprio(2);
+            // (issued at normal wave priority: raising it helped the loads
+            // through registers by 0.9 % on the 1024-microphone frame, but costs
+            // 0.5-0.9 % with the global-to-LDS copies)
             for (int i = wave; i < p.mic_block; i += W) {
                 const int mic = blk * p.mic_block + i;
                 Elem *dst = xwin + i * p.row;
@@ -829,7 +827,6 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
                     for (int r = lane; r < p.row; r += kWaveSize) dst[r] = Elem{};
                 }
             }
-            if (prio_staging) __builtin_amdgcn_s_setprio(0);
             // this wave's global-to-LDS copies have landed (vmcnt(0), the other
             // counters untouched; FP16/BF16 samples are staged through registers)
             if (ROOTS || p.dtype == 0) __builtin_amdgcn_s_waitcnt(0x0F70);
