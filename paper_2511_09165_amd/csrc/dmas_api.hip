@@ -646,13 +646,13 @@ dmas_status_t dmas_plan_create(const dmas_plan_desc_t *d, dmas_plan_t *out)
     // Per-block tables (each wave reads its block's offsets and reference
     // delays as scalars before the block's barrier, and the block's microphone
     // loop is straight-line code): always with more microphones than lanes;
-    // with fewer, for plain FP32 sums up to order 7, where they measured 1-3 %
-    // faster on the 32-microphone frame and 1.5-11 % on serving frames of
-    // 16-64 microphones (bitwise identical). At order 8 and with Kahan or
-    // FP64 sums, whose register budgets differ, the per-microphone reads one
-    // ahead stay (3-6 % faster there). DMAS_BLOCK_TABLES=0/1 overrides the
-    // choice for M <= 64 (tuning).
-    p->block_tables = M > dmas::kWaveSize || (p->compensated == DMAS_ACCUM_F32 && n <= 7);
+    // with fewer, for plain FP32 sums, where they measured 1-3 % faster on the
+    // 32-microphone frame and 1.5-11 % on serving frames of 16-64 microphones
+    // (bitwise identical; 1.8 % at order 8 once the windows are copied by
+    // global-to-LDS loads). With Kahan or FP64 sums, whose register budgets
+    // differ, the per-microphone reads one ahead stay (1.4-2.4 % faster
+    // there). DMAS_BLOCK_TABLES=0/1 overrides the choice for M <= 64 (tuning).
+    p->block_tables = M > dmas::kWaveSize || p->compensated == DMAS_ACCUM_F32;
     if (const char *bt = std::getenv("DMAS_BLOCK_TABLES"))
         p->block_tables = M > dmas::kWaveSize || std::atoi(bt) != 0;
     p->block_tables = p->block_tables && p->tables;
