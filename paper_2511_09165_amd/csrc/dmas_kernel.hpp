@@ -966,7 +966,7 @@ __device__ __forceinline__ void dmas_body(const KernelParams &p, const int tile,
 //    the cap cost 1.3-2.6 %).
 //  * 6 (80 VGPRs, three workgroups per CU): orders 7 and 8 with FP32 sums
 //    (83 and 95 VGPRs unconstrained) and Kahan / FP64 sums up to order 5 with
-//    scalar-cache tables (87-89). The cap spills 16-56 bytes per lane, which
+//    scalar-cache tables (87-89). The cap spills up to 56 bytes per lane, which
 //    costs less than the third workgroup gains: 9-17 % faster on the
 //    32-microphone frame, 10 % on the near-field frame at order 7. Also
 //    delays computed on the device (whole-sample or linear) with FP32 sums:
